@@ -1,0 +1,184 @@
+"""Benchmark of the HOME-LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: the 256^3 fully periodic decaying-turbulence configuration (seeded
+divergence-free random field on |k| <= 8, max |u| = 0.1 cs, rho = 1,
+tau = 0.51), advanced in both storage formats: the paper's 16-bit moments
+(the headline value) and FP32 moments.  A step is one fluid pass over every
+cell plus the boundary pass (empty here: no solids, all faces periodic).
+Inputs are resident in HBM before the timed region; K steps are timed between
+two device synchronisations with events on the stream the kernels run on.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel
+(the fluid pass: algorithmic bytes per launch / mean launch time from HIP
+events, against the 8 TB/s HBM peak; measured HBM traffic from rocprofv3
+counters when a summary for the current kernel source is committed), and the
+CPU oracle timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM peak, fp32 vs 16-bit moments; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+N = 256
+TAU = 0.51
+BYTES_PER_CELL = {"q16": 40, "fp32": 80}   # one state read + one state written
+KERNEL_SOURCES = ["paper_2602_05295_amd/csrc/lbm_fluid.hip", "paper_2602_05295_amd/csrc/lbm_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fluid_256cubed_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(fmt: str):
+    """HBM bytes per fluid launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or fmt not in t.get("formats", {}):
+        return None
+    return t["formats"][fmt]["hbm_bytes_per_launch"]
+
+
+def workload():
+    from paper_2602_05295_amd import workloads as W
+    u = W.random_solenoidal(N, N, N, 8.0, 0.1 * W.CS, seed=0).astype(np.float32)
+    rho = np.ones((N, N, N), np.float32)
+    return rho, u
+
+
+def run_format(fmt, rho_d, u_d, steps, warmup):
+    import torch
+    from paper_2602_05295_amd.homelbm import HomeLBM
+    stream = torch.cuda.current_stream()
+    with HomeLBM((N, N, N), TAU, fmt=fmt, stream=stream.cuda_stream) as s:
+        s.set_options(check_health=False, dither_mode=1, seed=0)
+        s.set_equilibrium(rho_d, u_d)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        s.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1)
+        bad = s.check()
+        # per-launch kernel time of the fluid pass (events around each launch)
+        prof = s.profile_steps(min(steps, 200))
+        state_bytes, _ = s.memory_bytes()
+    cells = N ** 3
+    fluid_ms = prof["fluid_ms"] / max(prof["fluid_launches"], 1)
+    achieved = cells * BYTES_PER_CELL[fmt] / (fluid_ms * 1e-3) / 1e9
+    return {
+        "mlups": cells * steps / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms / steps,
+        "wall_s": wall,
+        "fluid_kernel_ms": fluid_ms,
+        "achieved_GBs": achieved,
+        "hbm_frac": achieved / HBM_PEAK_GBS,
+        "state_bytes": state_bytes,
+        "unhealthy_values": int(bad),
+    }
+
+
+def cpu_baseline(u, steps=2):
+    """The FP64 oracle on the host, untuned: `steps` steps of the same 256^3
+    field on all host threads."""
+    import oracle
+    m = oracle.equilibrium_moments(np.ones((N, N, N)), u.astype(np.float64))
+    P = oracle.make_params((N, N, N), TAU)
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m = oracle.step(P, m, nthreads=threads)
+    dt = time.perf_counter() - t0
+    cells = N ** 3
+    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the full {N}^3 field, {dt:.1f} s on {threads} host threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    print(f"[bench] device {torch.cuda.get_device_name(0)}; building the {N}^3 field", file=sys.stderr, flush=True)
+    rho, u = workload()
+    rho_d = torch.from_numpy(rho).cuda()
+    u_d = torch.from_numpy(u).cuda()
+    res = {}
+    for fmt in ("q16", "fp32"):
+        res[fmt] = run_format(fmt, rho_d, u_d, args.steps, args.warmup)
+        print(f"[bench] {fmt}: {res[fmt]['mlups']:.0f} MLUPS, fluid kernel {res[fmt]['fluid_kernel_ms']:.4f} ms, "
+              f"{res[fmt]['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
+    print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(u)
+    q = res["q16"]
+    traffic = measured_traffic("q16")
+    line = {
+        "metric": METRIC,
+        "value": round(q["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(q["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "decaying turbulence 256^3 periodic, D3Q27 HOME-LBM, 16-bit moments",
+                   "grid": [N, N, N], "tau": TAU, "moments": "q16", "field": "solenoidal |k|<=8, max|u|=0.1cs",
+                   "dither": "per step"},
+        "roofline": {"bound": "hbm", "achieved": round(q["achieved_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(q["hbm_frac"], 4),
+                     "traffic": None if traffic is None else round(traffic / (q["fluid_kernel_ms"] * 1e-3) / 1e9, 1),
+                     "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": N ** 3 * BYTES_PER_CELL["q16"],
+                     "kernel": "fluid_kernel<Q16>", "bytes_per_cell": BYTES_PER_CELL["q16"]},
+        "fp32": {"value": round(res["fp32"]["mlups"], 1), "unit": "MLUPS",
+                 "ms_per_step": round(res["fp32"]["ms_per_step"], 5),
+                 "roofline": {"bound": "hbm", "achieved": round(res["fp32"]["achieved_GBs"], 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(res["fp32"]["hbm_frac"], 4),
+                              "kernel": "fluid_kernel<F32>", "bytes_per_cell": BYTES_PER_CELL["fp32"]}},
+        "memory_ratio_q16_fp32": res["q16"]["state_bytes"] / res["fp32"]["state_bytes"],
+        "adjoint_forward_ratio": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * homelbm.h -- C ABI of the MI355X HOME-LBM library (libhomelbm.so).
+ *
+ * One D3Q27 HOME-LBM time step per lbm_step iteration, after "High-Performance
+ * Moment-Encoded Lattice Boltzmann Method with Stability-Guided Quantization"
+ * (arXiv 2602.05295):
+ *   - state: per cell the ten moments of Eq. (rho_u_stress), Sec. 3.1:
+ *     rho, j = rho u (3) and P = rho S (6, S the Hermite second moment
+ *     sum (c c - cs^2 delta) f / rho), stored after streaming (Alg. 2);
+ *   - step: moment-space collision (App. A, force-free) -> third-order Hermite
+ *     reconstruction of f+ (Eq. three_order_f, Sec. 3.2) -> pull streaming
+ *     f_i(x) = f+_i(x - c_i) -> projection back to moments (Sec. 4.2, Alg. 2);
+ *   - boundaries in a separate pass over a compacted list of boundary cells
+ *     (the split of Sec. 4.2): halfway bounce-back against a voxel solid mask,
+ *     an inflow face at x = 0 using the moment boundary of Sec. 3.2
+ *     (rho^p = rho^x, S^p = u^p u^p + (S^x - u^x u^x)) with u^p = u_in, and a
+ *     zero-gradient outflow face at x = nx-1;
+ *   - storage either FP32 (ten float planes, 40 B/cell) or the 16-bit form of
+ *     Sec. 5.3 (rho in [0.8, 1.5], u in [-0.4, 0.4] and the non-equilibrium
+ *     stress rho S - rho u u in [-0.1, 0.1], b = 16 with dithering, two codes
+ *     per 32-bit word, five word planes, 20 B/cell).
+ *
+ * Conventions shared by every call
+ *   - Cell (x, y, z) has linear index x + nx * (y + ny * z) (x fastest).
+ *   - A moment field is ten planes of nx*ny*nz floats, plane order
+ *     rho, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz.
+ *   - Pointers passed with on_device = 1 are HIP device pointers (e.g. a torch
+ *     tensor's data_ptr); with on_device = 0 they are host pointers.  The
+ *     caller owns every pointer it passes; the library keeps none of them after
+ *     the call returns.  The context owns all device memory it allocates.
+ *   - Work is enqueued on the context's stream (lbm_set_stream, default the
+ *     null stream).  Calls that read into or write from host memory
+ *     synchronise that stream before returning.
+ *   - Every call returns an lbm_status.  No call aborts or throws across the
+ *     ABI; lbm_last_error(ctx) (or lbm_last_error(NULL) for a failed
+ *     lbm_create) gives a message for the last failure.
+ *   - Calls on one context are not thread-safe; distinct contexts are
+ *     independent.
+ */
+#ifndef HOMELBM_H
+#define HOMELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Moment storage formats. */
+enum lbm_moment_format {
+  LBM_MOMENTS_FP32 = 0, /* ten float planes */
+  LBM_MOMENTS_Q16 = 1   /* five uint32 planes of paired 16-bit codes (Sec. 5.3) */
+};
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = 1,   /* bad dimensions, tau, mask, pointer or size */
+  LBM_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
+  LBM_ERR_DEVICE = 3,        /* a HIP call failed (message names it) */
+  LBM_ERR_UNSUPPORTED = 4,   /* valid request this build does not implement */
+  LBM_ERR_UNSTABLE = 5       /* the state holds non-finite values or saturated codes */
+};
+
+/* Dither modes for the 16-bit encode (Sec. 5.3, "Dithering"). */
+enum lbm_dither_mode {
+  LBM_DITHER_OFF = 0,      /* round to nearest, half up */
+  LBM_DITHER_PER_STEP = 1, /* zero-mean uniform noise per (cell, step, component) */
+  LBM_DITHER_STATIC = 2    /* one spatial noise pattern reused every step */
+};
+
+typedef struct lbm_options {
+  int dither_mode;    /* lbm_dither_mode; default LBM_DITHER_PER_STEP */
+  uint32_t seed;      /* dither seed; default 0 */
+  int inflow;         /* 1: x = 0 is an inflow face and x = nx-1 an outflow face;
+                         0 (default): x is periodic.  y and z are always periodic. */
+  float u_in[3];      /* inflow velocity (used when inflow = 1) */
+  int check_health;   /* 1 (default): lbm_step scans the state once at its end and
+                         returns LBM_ERR_UNSTABLE if any stored value is non-finite
+                         (FP32) or any code sits at 0 or 65535 (Q16) */
+} lbm_options;
+
+/* Fills *opt with the defaults listed above. */
+int lbm_default_options(lbm_options* opt);
+
+/*
+ * Creates a context for an nx*ny*nz grid (dims[0..2] = nx, ny, nz, each >= 1,
+ * nx*ny*nz <= 2^30).  tau > 1/2 is the relaxation time of App. A (kinematic
+ * viscosity nu = (tau - 1/2)/3).  solid_mask is a host array of nx*ny*nz bytes,
+ * 0 = fluid, 1 = solid, or NULL for no solids; it is copied.  moment_format is
+ * an lbm_moment_format.  The state starts at rest (rho = 1, j = 0, P = 0).
+ * On success *out receives the context; on failure *out is set to NULL.
+ * Errors: LBM_ERR_INVALID_ARG (dims, tau, format, mask values other than 0/1),
+ * LBM_ERR_OUT_OF_MEMORY, LBM_ERR_DEVICE.
+ */
+int lbm_create(const int dims[3], double tau, const uint8_t* solid_mask, int moment_format, lbm_ctx** out);
+
+/* Releases the context and its device memory (after synchronising its stream). NULL is a no-op. */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Message for the last failed call on ctx, or of the calling thread's last failed lbm_create when ctx is NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Sets the hipStream_t (passed as void*) all later work is enqueued on; NULL selects the null stream. */
+int lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
+
+/*
+ * Sets options.  Turning inflow on requires nx >= 6 and no solid cell within
+ * two cells of the x faces (LBM_ERR_INVALID_ARG otherwise); the boundary-cell
+ * list is rebuilt when the face setting changes.
+ */
+int lbm_set_options(lbm_ctx* ctx, const lbm_options* opt);
+int lbm_get_options(const lbm_ctx* ctx, lbm_options* opt);
+
+/*
+ * Sets the state from a full moment field (ten planes, see conventions).  Q16
+ * contexts encode it without dither.  Solid cells are set to rest whatever m
+ * holds there.
+ */
+int lbm_set_moments(lbm_ctx* ctx, const float* m, int on_device);
+
+/*
+ * Sets the equilibrium state of given rho (one plane) and u (three planes
+ * ux, uy, uz): j = rho u, P = rho u u.  Solid cells are set to rest.
+ */
+int lbm_set_equilibrium(lbm_ctx* ctx, const float* rho, const float* u, int on_device);
+
+/*
+ * Advances n >= 0 time steps; each is one fluid pass over every cell followed
+ * by one boundary pass over the compacted boundary list.  Asynchronous on the
+ * context stream unless check_health is set (then it synchronises once at the
+ * end).  The dither of step t (t counts all steps since create or the last
+ * lbm_set_step_count) is drawn from (cell, t, seed).
+ */
+int lbm_step(lbm_ctx* ctx, int n);
+
+/* Writes the current state as a full moment field (ten planes); solid cells read as rest. */
+int lbm_get_moments(lbm_ctx* ctx, float* m, int on_device);
+
+/*
+ * Raw state copy.  FP32: ten float planes (40 B/cell) in the moment order
+ * above except that plane 0 holds rho - 1 (for precision); Q16: five uint32 planes
+ * (20 B/cell), word p of a cell packs code 2p in its low and code 2p+1 in its
+ * high half, code order rho, ux, uy, uz, Nxx, Nyy, Nzz, Nxy, Nxz, Nyz.
+ * bytes must equal lbm_raw_bytes().
+ */
+size_t lbm_raw_bytes(const lbm_ctx* ctx);
+int lbm_get_raw(lbm_ctx* ctx, void* out, size_t bytes, int on_device);
+int lbm_set_raw(lbm_ctx* ctx, const void* in, size_t bytes, int on_device);
+
+/* Step counter used by the dither. */
+int lbm_get_step_count(const lbm_ctx* ctx, uint64_t* t);
+int lbm_set_step_count(lbm_ctx* ctx, uint64_t t);
+
+/*
+ * Bytes of the two ping-pong state buffers (2 x 40 B or 2 x 20 B per cell:
+ * the 50% saving of Sec. 6.2.1) and of all device memory the context holds.
+ */
+int lbm_memory_bytes(const lbm_ctx* ctx, size_t* state_bytes, size_t* total_bytes);
+
+/* Sizes of the boundary list: fluid cells recomputed by the boundary pass and solid cells reset to rest. */
+int lbm_boundary_counts(const lbm_ctx* ctx, int64_t* fluid_cells, int64_t* solid_cells);
+
+/* Scans the state now; *bad receives the number of offending values (see check_health). */
+int lbm_check(lbm_ctx* ctx, uint64_t* bad);
+
+/* Waits for all work on the context stream. */
+int lbm_synchronize(lbm_ctx* ctx);
+
+/*
+ * Runs n steps like lbm_step while timing every kernel launch with HIP events
+ * on the context stream; returns the summed device time (ms) of the fluid
+ * passes and of the boundary passes, and the number of launches of each.
+ * Synchronises.
+ */
+int lbm_profile_steps(lbm_ctx* ctx, int n, double* fluid_ms, double* boundary_ms, int* fluid_launches,
+                      int* boundary_launches);
+
+/*
+ * Device-side dither generator, for known-answer tests: for each of the n
+ * host cell indices idx[k] writes the two 32-bit hash words of step t to
+ * h_out[2k], h_out[2k+1] (host).  Synchronous.
+ */
+int lbm_debug_dither(int n, const uint32_t* idx, uint32_t t, uint32_t seed, int mode, uint32_t* h_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOMELBM_H */

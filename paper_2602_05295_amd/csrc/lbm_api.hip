@@ -1,0 +1,498 @@
+// lbm_api.hip -- the C ABI declared in include/homelbm.h: context, buffers,
+// boundary list, step loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/homelbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+  int nx = 0, ny = 0, nz = 0;
+  int64_t N = 0;
+  double tau = 0.0;
+  int fmt = 0;
+  lbm_options opt{};
+  hipStream_t stream = nullptr;
+  void* buf[2] = {nullptr, nullptr};  // ping-pong state buffers
+  int cur = 0;
+  uint8_t* d_mask = nullptr;          // copy of the solid mask (nullptr: no solids)
+  uint32_t* d_cells = nullptr;        // boundary list
+  uint32_t* d_bits = nullptr;
+  int64_t n_fluid_b = 0, n_solid_b = 0;
+  uint32_t* d_counters = nullptr;     // 3 list counters
+  unsigned long long* d_bad = nullptr;
+  bool list_built = false;
+  int list_inflow = -1;
+  uint64_t t = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(lbm_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_err = msg;
+  return code;
+}
+
+int hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
+  const int code = (e == hipErrorOutOfMemory) ? LBM_ERR_OUT_OF_MEMORY : LBM_ERR_DEVICE;
+  return fail(c, code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t plane_bytes(const lbm_ctx* c) { return size_t(c->N) * 4; }
+int n_planes(const lbm_ctx* c) { return c->fmt == FMT_F32 ? 10 : 5; }
+size_t state_bytes(const lbm_ctx* c) { return plane_bytes(c) * n_planes(c); }
+
+void planes_of(const lbm_ctx* c, void* base, void* out[10]) {
+  for (int k = 0; k < 10; ++k) out[k] = (k < n_planes(c)) ? static_cast<char*>(base) + size_t(k) * plane_bytes(c) : nullptr;
+}
+
+Geometry geom(const lbm_ctx* c) { return Geometry{c->nx, c->ny, c->nz, c->opt.inflow}; }
+
+void free_list(lbm_ctx* c) {
+  if (c->d_cells) (void)hipFree(c->d_cells);
+  if (c->d_bits) (void)hipFree(c->d_bits);
+  c->d_cells = c->d_bits = nullptr;
+  c->n_fluid_b = c->n_solid_b = 0;
+  c->list_built = false;
+}
+
+// Builds the boundary list on the device: count pass, exact allocation, fill pass.
+int build_list(lbm_ctx* c) {
+  free_list(c);
+  const Geometry g = geom(c);
+  if (!c->d_mask && !g.inflow) {
+    c->list_built = true;
+    c->list_inflow = g.inflow;
+    return LBM_OK;
+  }
+  hipError_t e = hipMemsetAsync(c->d_counters, 0, 3 * sizeof(uint32_t), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync(counters)");
+  e = launch_classify(c->d_mask, g, c->d_counters, nullptr, nullptr, 0, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "classify (count)");
+  uint32_t cnt[3] = {0, 0, 0};
+  e = hipMemcpyAsync(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reading list counts");
+  const int64_t total = int64_t(cnt[0]) + cnt[1];
+  if (total > 0) {
+    e = hipMalloc(&c->d_cells, size_t(total) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_bits, size_t(total) * 4);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(boundary list)");
+    e = hipMemsetAsync(c->d_counters, 0, 3 * sizeof(uint32_t), c->stream);
+    if (e == hipSuccess) e = launch_classify(c->d_mask, g, c->d_counters, c->d_cells, c->d_bits, uint32_t(total), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "classify (fill)");
+  }
+  c->n_fluid_b = cnt[0];
+  c->n_solid_b = cnt[1];
+  c->list_built = true;
+  c->list_inflow = g.inflow;
+  return LBM_OK;
+}
+
+int check_faces(lbm_ctx* c, const lbm_options& o) {
+  if (!o.inflow) return LBM_OK;
+  if (c->nx < 6) return fail(c, LBM_ERR_INVALID_ARG, "inflow needs nx >= 6");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(o.u_in[a]) || std::fabs(o.u_in[a]) > 0.4f)
+      return fail(c, LBM_ERR_INVALID_ARG, "u_in must be finite with |u_in| <= 0.4");
+  return LBM_OK;
+}
+
+StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
+  StepParams p{};
+  void* pin[10];
+  planes_of(c, const_cast<void*>(in), pin);
+  void* pout[10];
+  planes_of(c, out, pout);
+  for (int k = 0; k < 10; ++k) {
+    p.in[k] = pin[k];
+    p.out[k] = pout[k];
+  }
+  p.g = geom(c);
+  p.om1 = float(1.0 - 1.0 / c->tau);
+  const int mode = c->fmt == FMT_Q16 ? c->opt.dither_mode : 0;
+  p.dither = mode != 0;
+  p.key = dither_key(uint32_t(c->t), c->opt.seed, mode);
+  for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
+  return p;
+}
+
+// One step: fluid pass then boundary pass, buffers swapped.
+int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
+  const StepParams p = step_params(c, c->buf[c->cur], c->buf[1 - c->cur]);
+  hipError_t e = hipSuccess;
+  if (ev) e = hipEventRecord(ev[0], c->stream);
+  if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->stream);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "fluid pass");
+  const int64_t n = c->n_fluid_b + c->n_solid_b;
+  if (n > 0) {
+    if (ev) e = hipEventRecord(ev[2], c->stream);
+    if (e == hipSuccess) e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, int(n), c->stream);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
+  }
+  c->cur = 1 - c->cur;
+  c->t += 1;
+  return LBM_OK;
+}
+
+int scan_health(lbm_ctx* c, uint64_t* bad) {
+  hipError_t e = hipMemsetAsync(c->d_bad, 0, sizeof(unsigned long long), c->stream);
+  void* pl[10];
+  planes_of(c, c->buf[c->cur], pl);
+  const void* cpl[10];
+  for (int k = 0; k < 10; ++k) cpl[k] = pl[k];
+  if (e == hipSuccess) e = launch_health(c->fmt, cpl, c->N, c->d_bad, c->stream);
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, c->d_bad, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "health scan");
+  *bad = h;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_default_options(lbm_options* o) {
+  if (!o) return LBM_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->dither_mode = LBM_DITHER_PER_STEP;
+  o->seed = 0;
+  o->inflow = 0;
+  o->check_health = 1;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_ctx** out) {
+  if (!out) return fail(nullptr, LBM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!dims) return fail(nullptr, LBM_ERR_INVALID_ARG, "dims is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "every dimension must be >= 1");
+  const int64_t N = int64_t(dims[0]) * dims[1] * dims[2];
+  if (N > (int64_t(1) << 30)) return fail(nullptr, LBM_ERR_INVALID_ARG, "nx*ny*nz must be <= 2^30");
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(nullptr, LBM_ERR_INVALID_ARG, "tau must be > 1/2");
+  if (fmt != LBM_MOMENTS_FP32 && fmt != LBM_MOMENTS_Q16)
+    return fail(nullptr, LBM_ERR_INVALID_ARG, "unknown moment format");
+  bool any_solid = false;
+  if (mask) {
+    for (int64_t k = 0; k < N; ++k) {
+      if (mask[k] > 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "mask values must be 0 or 1");
+      any_solid = any_solid || mask[k];
+    }
+  }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(nullptr, LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->nx = dims[0];
+  c->ny = dims[1];
+  c->nz = dims[2];
+  c->N = N;
+  c->tau = tau;
+  c->fmt = fmt;
+  lbm_default_options(&c->opt);
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], state_bytes(c));
+  if (e == hipSuccess) e = hipMalloc(&c->d_counters, 4 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned long long));
+  if (e == hipSuccess && any_solid) {
+    e = hipMalloc(&c->d_mask, size_t(N));
+    if (e == hipSuccess) e = hipMemcpy(c->d_mask, mask, size_t(N), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    hip_fail(nullptr, e, "lbm_create allocation");
+    const int code = (e == hipErrorOutOfMemory) ? LBM_ERR_OUT_OF_MEMORY : LBM_ERR_DEVICE;
+    lbm_destroy(c);
+    return code;
+  }
+  // rest state
+  void* pl[10];
+  planes_of(c, c->buf[0], pl);
+  e = launch_set_rest(fmt, pl, c->N, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    hip_fail(nullptr, e, "lbm_create initial state");
+    lbm_destroy(c);
+    return LBM_ERR_DEVICE;
+  }
+  const int r = build_list(c);
+  if (r != LBM_OK) {
+    g_err = c->err;
+    lbm_destroy(c);
+    return r;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (int b = 0; b < 2; ++b)
+    if (c->buf[b]) hipFree(c->buf[b]);
+  if (c->d_mask) hipFree(c->d_mask);
+  free_list(c);
+  if (c->d_counters) hipFree(c->d_counters);
+  if (c->d_bad) hipFree(c->d_bad);
+  delete c;
+  return LBM_OK;
+}
+
+int lbm_set_stream(lbm_ctx* c, void* s) {
+  if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
+  c->stream = static_cast<hipStream_t>(s);
+  return LBM_OK;
+}
+
+int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
+  if (!c || !o) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  if (o->dither_mode < 0 || o->dither_mode > 2) return fail(c, LBM_ERR_INVALID_ARG, "unknown dither mode");
+  int r = check_faces(c, *o);
+  if (r != LBM_OK) return r;
+  if (o->inflow && c->d_mask) {
+    // no solid cell within two cells of the x faces
+    const int64_t plane = int64_t(c->nx);
+    std::vector<uint8_t> h(size_t(c->N));
+    hipError_t e = hipMemcpy(h.data(), c->d_mask, size_t(c->N), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "reading mask");
+    for (int64_t k = 0; k < c->N; ++k) {
+      const int x = int(k % plane);
+      if (h[size_t(k)] && (x < 3 || x > c->nx - 4))
+        return fail(c, LBM_ERR_INVALID_ARG, "solid cells within two cells of an open x face");
+    }
+  }
+  const int old_inflow = c->opt.inflow;
+  c->opt = *o;
+  if (!c->list_built || old_inflow != o->inflow) {
+    r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  return LBM_OK;
+}
+
+int lbm_get_options(const lbm_ctx* c, lbm_options* o) {
+  if (!c || !o) return LBM_ERR_INVALID_ARG;
+  *o = c->opt;
+  return LBM_OK;
+}
+
+static int stage_in(lbm_ctx* c, const void* src, size_t bytes, int on_device, void** dev, bool* owned) {
+  *owned = false;
+  if (on_device) {
+    *dev = const_cast<void*>(src);
+    return LBM_OK;
+  }
+  hipError_t e = hipMalloc(dev, bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(*dev, src, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "staging host input");
+  *owned = true;
+  return LBM_OK;
+}
+
+int lbm_set_moments(lbm_ctx* c, const float* m, int on_device) {
+  if (!c || !m) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  void* dm;
+  bool owned;
+  int r = stage_in(c, m, size_t(c->N) * 40, on_device, &dm, &owned);
+  if (r != LBM_OK) return r;
+  void* pl[10];
+  planes_of(c, c->buf[c->cur], pl);
+  hipError_t e = launch_set_moments(c->fmt, static_cast<const float*>(dm), pl, c->d_mask, c->N, c->stream);
+  if (e == hipSuccess && owned) e = hipStreamSynchronize(c->stream);
+  if (owned) hipFree(dm);
+  if (e != hipSuccess) return hip_fail(c, e, "set_moments");
+  return LBM_OK;
+}
+
+int lbm_set_equilibrium(lbm_ctx* c, const float* rho, const float* u, int on_device) {
+  if (!c || !rho || !u) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  void *dr, *du;
+  bool o1, o2;
+  int r = stage_in(c, rho, size_t(c->N) * 4, on_device, &dr, &o1);
+  if (r != LBM_OK) return r;
+  r = stage_in(c, u, size_t(c->N) * 12, on_device, &du, &o2);
+  if (r != LBM_OK) {
+    if (o1) hipFree(dr);
+    return r;
+  }
+  void* pl[10];
+  planes_of(c, c->buf[c->cur], pl);
+  hipError_t e = launch_set_equilibrium(c->fmt, static_cast<const float*>(dr), static_cast<const float*>(du), pl,
+                                        c->d_mask, c->N, c->stream);
+  if (e == hipSuccess && (o1 || o2)) e = hipStreamSynchronize(c->stream);
+  if (o1) hipFree(dr);
+  if (o2) hipFree(du);
+  if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium");
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int n) {
+  if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 0) return fail(c, LBM_ERR_INVALID_ARG, "n must be >= 0");
+  if (!c->list_built) {
+    const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  for (int s = 0; s < n; ++s) {
+    const int r = enqueue_step(c, nullptr);
+    if (r != LBM_OK) return r;
+  }
+  if (c->opt.check_health && n > 0) {
+    uint64_t bad = 0;
+    const int r = scan_health(c, &bad);
+    if (r != LBM_OK) return r;
+    if (bad) return fail(c, LBM_ERR_UNSTABLE, "state holds " + std::to_string(bad) + " non-finite or saturated values");
+  }
+  return LBM_OK;
+}
+
+int lbm_get_moments(lbm_ctx* c, float* m, int on_device) {
+  if (!c || !m) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  float* dm = m;
+  hipError_t e = hipSuccess;
+  if (!on_device) e = hipMalloc(&dm, size_t(c->N) * 40);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(get_moments staging)");
+  void* pl[10];
+  planes_of(c, c->buf[c->cur], pl);
+  const void* cpl[10];
+  for (int k = 0; k < 10; ++k) cpl[k] = pl[k];
+  e = launch_get_moments(c->fmt, cpl, dm, c->d_mask, c->N, c->stream);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(m, dm, size_t(c->N) * 40, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
+  if (!on_device) hipFree(dm);
+  if (e != hipSuccess) return hip_fail(c, e, "get_moments");
+  return LBM_OK;
+}
+
+size_t lbm_raw_bytes(const lbm_ctx* c) { return c ? state_bytes(c) : 0; }
+
+int lbm_get_raw(lbm_ctx* c, void* out, size_t bytes, int on_device) {
+  if (!c || !out) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  if (bytes != state_bytes(c)) return fail(c, LBM_ERR_INVALID_ARG, "bytes must equal lbm_raw_bytes()");
+  hipError_t e = hipMemcpyAsync(out, c->buf[c->cur], bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "get_raw");
+  return LBM_OK;
+}
+
+int lbm_set_raw(lbm_ctx* c, const void* in, size_t bytes, int on_device) {
+  if (!c || !in) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  if (bytes != state_bytes(c)) return fail(c, LBM_ERR_INVALID_ARG, "bytes must equal lbm_raw_bytes()");
+  hipError_t e = hipMemcpyAsync(c->buf[c->cur], in, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                c->stream);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "set_raw");
+  return LBM_OK;
+}
+
+int lbm_get_step_count(const lbm_ctx* c, uint64_t* t) {
+  if (!c || !t) return LBM_ERR_INVALID_ARG;
+  *t = c->t;
+  return LBM_OK;
+}
+
+int lbm_set_step_count(lbm_ctx* c, uint64_t t) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  c->t = t;
+  return LBM_OK;
+}
+
+int lbm_memory_bytes(const lbm_ctx* c, size_t* sb, size_t* tb) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  const size_t s = 2 * state_bytes(c);
+  if (sb) *sb = s;
+  if (tb) *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + 4 * 4 + 8;
+  return LBM_OK;
+}
+
+int lbm_boundary_counts(const lbm_ctx* c, int64_t* fl, int64_t* so) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  if (fl) *fl = c->n_fluid_b;
+  if (so) *so = c->n_solid_b;
+  return LBM_OK;
+}
+
+int lbm_check(lbm_ctx* c, uint64_t* bad) {
+  if (!c || !bad) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  const int r = scan_health(c, bad);
+  if (r != LBM_OK) return r;
+  return *bad ? LBM_ERR_UNSTABLE : LBM_OK;
+}
+
+int lbm_synchronize(lbm_ctx* c) {
+  if (!c) return LBM_ERR_INVALID_ARG;
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(c, e, "hipStreamSynchronize");
+}
+
+int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, int* nf, int* nb) {
+  if (!c || n < 0) return fail(c, LBM_ERR_INVALID_ARG, "bad argument");
+  if (!c->list_built) {
+    const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  const bool has_b = (c->n_fluid_b + c->n_solid_b) > 0;
+  std::vector<hipEvent_t> ev(size_t(4) * n);
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+  int r = LBM_OK;
+  for (int s = 0; s < n && r == LBM_OK; ++s) r = enqueue_step(c, &ev[size_t(4) * s]);
+  if (r == LBM_OK) e = hipStreamSynchronize(c->stream);
+  double tf = 0, tb = 0;
+  for (int s = 0; s < n && r == LBM_OK && e == hipSuccess; ++s) {
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, ev[size_t(4) * s], ev[size_t(4) * s + 1]);
+    tf += ms;
+    if (has_b && e == hipSuccess) {
+      e = hipEventElapsedTime(&ms, ev[size_t(4) * s + 2], ev[size_t(4) * s + 3]);
+      tb += ms;
+    }
+  }
+  for (auto& x : ev) hipEventDestroy(x);
+  if (r != LBM_OK) return r;
+  if (e != hipSuccess) return hip_fail(c, e, "profiling events");
+  if (fluid_ms) *fluid_ms = tf;
+  if (boundary_ms) *boundary_ms = tb;
+  if (nf) *nf = n;
+  if (nb) *nb = has_b ? n : 0;
+  return LBM_OK;
+}
+
+int lbm_debug_dither(int n, const uint32_t* idx, uint32_t t, uint32_t seed, int mode, uint32_t* h_out) {
+  if (n < 0 || (n > 0 && (!idx || !h_out))) return fail(nullptr, LBM_ERR_INVALID_ARG, "bad argument");
+  if (n == 0) return LBM_OK;
+  uint32_t *d_idx = nullptr, *d_out = nullptr;
+  hipError_t e = hipMalloc(&d_idx, size_t(n) * 4);
+  if (e == hipSuccess) e = hipMalloc(&d_out, size_t(n) * 8);
+  if (e == hipSuccess) e = hipMemcpy(d_idx, idx, size_t(n) * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_debug_dither(n, d_idx, dither_key(t, seed, mode), d_out, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(h_out, d_out, size_t(n) * 8, hipMemcpyDeviceToHost);
+  if (d_idx) hipFree(d_idx);
+  if (d_out) hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "debug_dither");
+  return LBM_OK;
+}
+
+}  // extern "C"

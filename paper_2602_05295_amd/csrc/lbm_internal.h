@@ -1,0 +1,55 @@
+// lbm_internal.h -- host-side declarations shared by the runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Format { FMT_F32 = 0, FMT_Q16 = 1 };
+
+// Boundary-list entry flags (bits 0..26 mark links i whose source x - c_i is solid).
+constexpr uint32_t BIT_INFLOW = 1u << 27;   // cell on the inflow face x = 0
+constexpr uint32_t BIT_OUTFLOW = 1u << 28;  // cell on the outflow face x = nx-1
+constexpr uint32_t BIT_SOLID = 1u << 29;    // solid cell next to fluid: reset to rest
+
+struct Geometry {
+  int nx, ny, nz;
+  int inflow;
+};
+
+struct StepParams {
+  const void* in[10];  // state planes read (FP32: 10 float planes, Q16: 5 word planes)
+  void* out[10];       // state planes written
+  Geometry g;
+  int zchunk;
+  float om1;           // 1 - 1/tau
+  uint32_t key;        // dither key of this step
+  int dither;          // 0: round to nearest; else add the dither of `key`
+  float u_in[3];
+};
+
+// Fused fluid pass over every cell (all axes treated periodic).
+hipError_t launch_fluid(int fmt, const StepParams& p, hipStream_t s);
+void fluid_tiling(const Geometry& g, dim3* grid, dim3* block, int* zchunk);
+
+// Boundary pass over the compacted list.
+hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits, int count,
+                           hipStream_t s);
+
+// Boundary list: count pass (cells == nullptr) or fill pass.
+hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t* counters, uint32_t* cells,
+                           uint32_t* bits, uint32_t capacity, hipStream_t s);
+
+// Codec / initialisation / read-back.
+hipError_t launch_set_moments(int fmt, const float* m, void* const out[10], const uint8_t* mask, int64_t N,
+                              hipStream_t s);
+hipError_t launch_set_equilibrium(int fmt, const float* rho, const float* u, void* const out[10],
+                                  const uint8_t* mask, int64_t N, hipStream_t s);
+hipError_t launch_get_moments(int fmt, const void* const in[10], float* m, const uint8_t* mask, int64_t N,
+                              hipStream_t s);
+hipError_t launch_set_rest(int fmt, void* const out[10], int64_t N, hipStream_t s);
+hipError_t launch_health(int fmt, const void* const in[10], int64_t N, unsigned long long* bad, hipStream_t s);
+hipError_t launch_debug_dither(int n, const uint32_t* idx, uint32_t key, uint32_t* out, hipStream_t s);
+
+}  // namespace lbm

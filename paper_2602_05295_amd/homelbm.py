@@ -1,0 +1,287 @@
+"""ctypes binding of libhomelbm.so (include/homelbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Arrays may be numpy arrays (host) or torch CUDA tensors (device); torch is
+used only for device memory and streams.  There is no CPU fallback: if the
+library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhomelbm.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "homelbm.h")
+
+FP32, Q16 = 0, 1
+DITHER_OFF, DITHER_PER_STEP, DITHER_STATIC = 0, 1, 2
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED, ERR_UNSTABLE = range(6)
+_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "UNSUPPORTED", 5: "UNSTABLE"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("dither_mode", ctypes.c_int),
+        ("seed", ctypes.c_uint32),
+        ("inflow", ctypes.c_int),
+        ("u_in", ctypes.c_float * 3),
+        ("check_health", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def declared_functions():
+    """Names of the functions include/homelbm.h declares."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """Loads libhomelbm.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_05295_amd.build` "
+                           "(or __graft_entry__.build()); there is no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.lbm_default_options.argtypes = [P(Options)]
+    L.lbm_create.argtypes = [P(ctypes.c_int), ctypes.c_double, vp, i, P(vp)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_set_stream.argtypes = [vp, vp]
+    L.lbm_set_options.argtypes = [vp, P(Options)]
+    L.lbm_get_options.argtypes = [vp, P(Options)]
+    L.lbm_set_moments.argtypes = [vp, vp, i]
+    L.lbm_set_equilibrium.argtypes = [vp, vp, vp, i]
+    L.lbm_step.argtypes = [vp, i]
+    L.lbm_get_moments.argtypes = [vp, vp, i]
+    L.lbm_raw_bytes.argtypes = [vp]
+    L.lbm_raw_bytes.restype = sz
+    L.lbm_get_raw.argtypes = [vp, vp, sz, i]
+    L.lbm_set_raw.argtypes = [vp, vp, sz, i]
+    L.lbm_get_step_count.argtypes = [vp, P(ctypes.c_uint64)]
+    L.lbm_set_step_count.argtypes = [vp, ctypes.c_uint64]
+    L.lbm_memory_bytes.argtypes = [vp, P(sz), P(sz)]
+    L.lbm_boundary_counts.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    L.lbm_check.argtypes = [vp, P(ctypes.c_uint64)]
+    L.lbm_synchronize.argtypes = [vp]
+    L.lbm_profile_steps.argtypes = [vp, i, P(ctypes.c_double), P(ctypes.c_double), P(i), P(i)]
+    L.lbm_debug_dither.argtypes = [i, vp, ctypes.c_uint32, ctypes.c_uint32, i, vp]
+    _lib = L
+    return L
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, dtype, count):
+    """(pointer, on_device, keepalive) for a numpy array or a torch CUDA tensor."""
+    if _is_torch(a):
+        if not a.is_cuda or not a.is_contiguous():
+            raise ValueError("torch tensors must be contiguous CUDA tensors")
+        if a.numel() != count or a.element_size() != np.dtype(dtype).itemsize:
+            raise ValueError(f"tensor must hold {count} values of {np.dtype(dtype)}")
+        return ctypes.c_void_p(a.data_ptr()), 1, a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.size != count:
+        raise ValueError(f"array must hold {count} values, has {arr.size}")
+    return arr.ctypes.data_as(ctypes.c_void_p), 0, arr
+
+
+def debug_dither(idx, t, seed, mode):
+    """Device-side dither hash words (n, 2) for host cell indices idx."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    out = np.zeros((idx.size, 2), dtype=np.uint32)
+    st = lib().lbm_debug_dither(idx.size, idx.ctypes.data_as(ctypes.c_void_p), t, seed, mode,
+                                out.ctypes.data_as(ctypes.c_void_p))
+    if st != OK:
+        raise LBMError(st, lib().lbm_last_error(None).decode())
+    return out
+
+
+class HomeLBM:
+    """One HOME-LBM domain on the current HIP device."""
+
+    def __init__(self, dims, tau, mask=None, fmt="fp32", stream=None, **options):
+        L = lib()
+        self.dims = tuple(int(d) for d in dims)
+        self.N = int(np.prod(self.dims))
+        self.fmt = {"fp32": FP32, "q16": Q16, FP32: FP32, Q16: Q16}[fmt]
+        d = (ctypes.c_int * 3)(*self.dims)
+        self._mask = None
+        mp = None
+        if mask is not None:
+            self._mask = np.ascontiguousarray(mask, dtype=np.uint8)
+            if self._mask.size != self.N:
+                raise ValueError("mask must have nx*ny*nz entries")
+            mp = self._mask.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        self._h = None
+        self._check(L.lbm_create(d, float(tau), mp, self.fmt, ctypes.byref(h)), None)
+        self._h = h
+        self.tau = float(tau)
+        if stream is None:
+            stream = _torch_stream()
+        if stream is not None:
+            self._check(L.lbm_set_stream(self._h, ctypes.c_void_p(stream)))
+        if options:
+            self.set_options(**options)
+
+    # -- plumbing
+    def _check(self, st, h="self"):
+        if st != OK:
+            handle = self._h if h == "self" else h
+            msg = lib().lbm_last_error(handle)
+            raise LBMError(st, msg.decode() if msg else "")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- options
+    def options(self) -> Options:
+        o = Options()
+        self._check(lib().lbm_get_options(self._h, ctypes.byref(o)))
+        return o
+
+    def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None):
+        o = self.options()
+        if dither_mode is not None:
+            o.dither_mode = int(dither_mode)
+        if seed is not None:
+            o.seed = int(seed) & 0xFFFFFFFF
+        if inflow is not None:
+            o.inflow = int(bool(inflow))
+        if u_in is not None:
+            o.u_in = (ctypes.c_float * 3)(*[float(v) for v in u_in])
+        if check_health is not None:
+            o.check_health = int(bool(check_health))
+        self._check(lib().lbm_set_options(self._h, ctypes.byref(o)))
+
+    def set_stream(self, stream):
+        self._check(lib().lbm_set_stream(self._h, ctypes.c_void_p(stream or 0)))
+
+    # -- state
+    def set_moments(self, m):
+        p, dev, keep = _ptr(m, np.float32, 10 * self.N)
+        self._check(lib().lbm_set_moments(self._h, p, dev))
+
+    def set_equilibrium(self, rho, u):
+        p1, d1, k1 = _ptr(rho, np.float32, self.N)
+        p2, d2, k2 = _ptr(u, np.float32, 3 * self.N)
+        if d1 != d2:
+            raise ValueError("rho and u must both be host arrays or both device tensors")
+        self._check(lib().lbm_set_equilibrium(self._h, p1, p2, d1))
+
+    def get_moments(self, out=None):
+        """(10, nz, ny, nx) float32 numpy array, or fills a torch CUDA tensor."""
+        if out is None:
+            out = np.empty((10,) + self.dims[::-1], dtype=np.float32)
+        p, dev, keep = _ptr(out, np.float32, 10 * self.N)
+        self._check(lib().lbm_get_moments(self._h, p, dev))
+        return out
+
+    def raw_bytes(self):
+        return int(lib().lbm_raw_bytes(self._h))
+
+    def get_raw(self, out=None):
+        """Raw state: FP32 (10, nz, ny, nx) float32, Q16 (5, nz, ny, nx) uint32."""
+        shape, dt = ((10,) + self.dims[::-1], np.float32) if self.fmt == FP32 else ((5,) + self.dims[::-1], np.uint32)
+        if out is None:
+            out = np.empty(shape, dtype=dt)
+        p, dev, keep = _ptr(out, dt, int(np.prod(shape)))
+        self._check(lib().lbm_get_raw(self._h, p, self.raw_bytes(), dev))
+        return out
+
+    def set_raw(self, raw):
+        dt = np.float32 if self.fmt == FP32 else np.uint32
+        n = (10 if self.fmt == FP32 else 5) * self.N
+        p, dev, keep = _ptr(raw, dt, n)
+        self._check(lib().lbm_set_raw(self._h, p, self.raw_bytes(), dev))
+
+    # -- stepping
+    def step(self, n=1):
+        self._check(lib().lbm_step(self._h, int(n)))
+
+    def synchronize(self):
+        self._check(lib().lbm_synchronize(self._h))
+
+    @property
+    def step_count(self):
+        t = ctypes.c_uint64()
+        self._check(lib().lbm_get_step_count(self._h, ctypes.byref(t)))
+        return t.value
+
+    @step_count.setter
+    def step_count(self, t):
+        self._check(lib().lbm_set_step_count(self._h, int(t)))
+
+    def memory_bytes(self):
+        s, t = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(lib().lbm_memory_bytes(self._h, ctypes.byref(s), ctypes.byref(t)))
+        return s.value, t.value
+
+    def boundary_counts(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().lbm_boundary_counts(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def check(self):
+        bad = ctypes.c_uint64()
+        st = lib().lbm_check(self._h, ctypes.byref(bad))
+        if st not in (OK, ERR_UNSTABLE):
+            self._check(st)
+        return bad.value
+
+    def profile_steps(self, n):
+        """Runs n steps with per-kernel HIP events: dict of summed ms and launch counts."""
+        f, b = ctypes.c_double(), ctypes.c_double()
+        nf, nb = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().lbm_profile_steps(self._h, int(n), ctypes.byref(f), ctypes.byref(b), ctypes.byref(nf),
+                                            ctypes.byref(nb)))
+        return {"fluid_ms": f.value, "boundary_ms": b.value, "fluid_launches": nf.value,
+                "boundary_launches": nb.value}
+
+
+def _torch_stream():
+    """The current torch stream handle if torch with HIP is usable, else None."""
+    try:
+        import torch
+    except ImportError:
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream().cuda_stream
