@@ -103,9 +103,88 @@ def run_format(fmt, rho_d, u_d, steps, warmup):
     }
 
 
-def cpu_baseline(u, steps=2):
+def adjoint_ratio(n=128, steps=400, every=20):
+    """(recompute + adjoint) / forward wall time of a checkpointed rollout on
+    the 128^3 box with ~5% sphere obstacles (FP32, tau = 0.6); loss = L2 of
+    the final velocity against a second seeded field."""
+    import torch
+    from paper_2602_05295_amd import workloads as W
+    from paper_2602_05295_amd.adjoint import rollout
+    from paper_2602_05295_amd.homelbm import HomeLBM
+    mask = W.sphere_mask(n, n, n, phi=0.05, rmin=4.0, rmax=12.0, seed=0)
+    u0 = torch.tensor(W.random_solenoidal(n, n, n, 4.0, 0.05, seed=0), dtype=torch.float32, device="cuda")
+    tgt = torch.tensor(W.random_solenoidal(n, n, n, 4.0, 0.05, seed=1), dtype=torch.float32, device="cuda")
+    fl = torch.tensor(mask == 0, dtype=torch.float32, device="cuda")
+    with HomeLBM((n, n, n), 0.6, mask=mask) as s:
+        s.set_options(check_health=False)
+        u = u0.clone().requires_grad_(True)
+        for rep in range(2):  # the first pass warms up
+            u.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = rollout(s, u, steps, every)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            vel = out[1:4] / out[0]
+            loss = 0.5 * (((vel - tgt) ** 2).sum(0) * fl).sum()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            loss.backward()
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+        fwd, bwd = t1 - t0, t3 - t2
+        # the forward alone, without checkpoint copies
+        s.set_equilibrium(torch.ones((n, n, n), device="cuda"), u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        plain = time.perf_counter() - t0
+    return {"config": f"{n}^3 box, {float(mask.mean()):.3f} solid, FP32, tau 0.6, {steps} steps, checkpoint every {every}",
+            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "forward_plain_s": round(plain, 4),
+            "ratio": round(bwd / plain, 3), "grad_finite": bool(torch.isfinite(u.grad).all())}
+
+
+def channel(steps=20):
+    """The 1000x400x400 obstacle channel in 16-bit moments: fluid + boundary
+    passes per step (MLUPS over all cells) and the two kernels' times."""
+    import torch
+    from paper_2602_05295_amd import workloads as W
+    from paper_2602_05295_amd.homelbm import HomeLBM
+    nx, ny, nz = 1000, 400, 400
+    mask = W.channel_mask(nx, ny, nz, seed=0)
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float32, device="cuda")
+    u[0] = 0.08
+    u[:, torch.from_numpy(mask).cuda().bool()] = 0.0
+    rho = torch.ones((nz, ny, nx), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    with HomeLBM((nx, ny, nz), 0.52, mask=mask, fmt="q16", stream=stream.cuda_stream) as s:
+        s.set_options(check_health=False, inflow=True, u_in=(0.08, 0.0, 0.0))
+        s.set_equilibrium(rho, u)
+        del u, rho
+        s.step(5)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        prof = s.profile_steps(steps)
+        nf, ns = s.boundary_counts()
+        bad = s.check()
+    cells = nx * ny * nz
+    return {"config": "1000x400x400 channel, 16-bit, tau 0.52, inflow 0.08, 300 obstacles",
+            "solid_fraction": round(float(mask.mean()), 4), "boundary_fluid_cells": nf, "boundary_solid_cells": ns,
+            "mlups": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "fluid_kernel_ms": round(prof["fluid_ms"] / prof["fluid_launches"], 4),
+            "boundary_kernel_ms": round(prof["boundary_ms"] / max(prof["boundary_launches"], 1), 4),
+            "unhealthy_values": int(bad)}
+
+
+def cpu_baseline(u, steps=8):
     """The FP64 oracle on the host, untuned: `steps` steps of the same 256^3
-    field on all host threads."""
+    field on all host threads (about 10-20 s)."""
     import oracle
     m = oracle.equilibrium_moments(np.ones((N, N, N)), u.astype(np.float64))
     P = oracle.make_params((N, N, N), TAU)
@@ -125,6 +204,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--formats", default="q16,fp32", help="storage formats to run (the headline value is q16)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint ratio and the channel run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path; "
@@ -139,12 +220,23 @@ def main():
     rho_d = torch.from_numpy(rho).cuda()
     u_d = torch.from_numpy(u).cuda()
     res = {}
-    for fmt in ("q16", "fp32"):
+    for fmt in args.formats.split(","):
         res[fmt] = run_format(fmt, rho_d, u_d, args.steps, args.warmup)
         print(f"[bench] {fmt}: {res[fmt]['mlups']:.0f} MLUPS, fluid kernel {res[fmt]['fluid_kernel_ms']:.4f} ms, "
               f"{res[fmt]['achieved_GBs']:.0f} GB/s", file=sys.stderr, flush=True)
+    extras = {}
+    if not args.no_extras:
+        print("[bench] adjoint/forward ratio (128^3, 400 steps)", file=sys.stderr, flush=True)
+        extras["adjoint"] = adjoint_ratio()
+        print(f"[bench] {extras['adjoint']}", file=sys.stderr, flush=True)
+        print("[bench] 1000x400x400 channel", file=sys.stderr, flush=True)
+        extras["channel"] = channel()
+        print(f"[bench] {extras['channel']}", file=sys.stderr, flush=True)
     print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u)
+    if "q16" not in res or "fp32" not in res:
+        print(json.dumps({k: v for k, v in res.items()}), flush=True)
+        return
     q = res["q16"]
     traffic = measured_traffic("q16")
     line = {
@@ -174,7 +266,9 @@ def main():
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(res["fp32"]["hbm_frac"], 4),
                               "kernel": "fluid_kernel<F32>", "bytes_per_cell": BYTES_PER_CELL["fp32"]}},
         "memory_ratio_q16_fp32": res["q16"]["state_bytes"] / res["fp32"]["state_bytes"],
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": extras.get("adjoint", {}).get("ratio"),
+        "adjoint": extras.get("adjoint"),
+        "channel_1000x400x400": extras.get("channel"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -166,6 +166,32 @@ int lbm_boundary_counts(const lbm_ctx* ctx, int64_t* fluid_cells, int64_t* solid
 /* Scans the state now; *bad receives the number of offending values (see check_health). */
 int lbm_check(lbm_ctx* ctx, uint64_t* bad);
 
+/*
+ * Adjoint of one step, for gradients through lbm_step (FP32 contexts only,
+ * else LBM_ERR_UNSUPPORTED).  All pointers are device pointers to ten planes
+ * of nx*ny*nz floats:
+ *   m_t      the raw FP32 state the step was taken from (the lbm_get_raw
+ *            layout: plane 0 holds rho - 1);
+ *   lam_next the adjoint of the moments after the step (moment order; the
+ *            adjoint of rho equals that of rho - 1);
+ *   lam_prev receives J(m_t)^T lam_next, the adjoint of the moments before the
+ *            step (zero at solid cells).  It must not alias the inputs.
+ * It follows the same step as lbm_step: App. A collision, the third-order
+ * reconstruction of Eq. (three_order_f), pull streaming, projection, and the
+ * boundary rules (bounce-back, inflow, outflow).  Asynchronous on the context
+ * stream.  Contributions through boundary cells are added with float atomics,
+ * so the last bits can vary between runs.
+ */
+int lbm_adjoint_step(lbm_ctx* ctx, const float* m_t, const float* lam_next, float* lam_prev);
+
+/*
+ * Vector-Jacobian product of lbm_set_equilibrium's map (rho, u) -> (rho, rho u,
+ * rho u u): given lam (ten planes), writes grad_rho (one plane; may be NULL)
+ * and grad_u (three planes); zero at solid cells.  Device pointers, async.
+ */
+int lbm_equilibrium_vjp(lbm_ctx* ctx, const float* rho, const float* u, const float* lam, float* grad_rho,
+                        float* grad_u);
+
 /* Waits for all work on the context stream. */
 int lbm_synchronize(lbm_ctx* ctx);
 

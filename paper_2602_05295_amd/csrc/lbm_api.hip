@@ -30,6 +30,8 @@ struct lbm_ctx {
   int64_t n_fluid_b = 0, n_solid_b = 0;
   uint32_t* d_counters = nullptr;     // 3 list counters
   unsigned long long* d_bad = nullptr;
+  uint8_t* d_flags = nullptr;         // adjoint cell flags (built on first use)
+  bool flags_valid = false;
   bool list_built = false;
   int list_inflow = -1;
   uint64_t t = 0;
@@ -69,6 +71,7 @@ void free_list(lbm_ctx* c) {
   c->d_cells = c->d_bits = nullptr;
   c->n_fluid_b = c->n_solid_b = 0;
   c->list_built = false;
+  c->flags_valid = false;
 }
 
 // Builds the boundary list on the device: count pass, exact allocation, fill pass.
@@ -252,8 +255,9 @@ int lbm_destroy(lbm_ctx* c) {
     if (c->buf[b]) hipFree(c->buf[b]);
   if (c->d_mask) hipFree(c->d_mask);
   free_list(c);
-  if (c->d_counters) hipFree(c->d_counters);
-  if (c->d_bad) hipFree(c->d_bad);
+  if (c->d_counters) (void)hipFree(c->d_counters);
+  if (c->d_bad) (void)hipFree(c->d_bad);
+  if (c->d_flags) (void)hipFree(c->d_flags);
   delete c;
   return LBM_OK;
 }
@@ -477,6 +481,48 @@ int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, 
   if (boundary_ms) *boundary_ms = tb;
   if (nf) *nf = n;
   if (nb) *nb = has_b ? n : 0;
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float* lam_prev) {
+  if (!c || !m_t || !lam_next || !lam_prev) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  if (c->fmt != FMT_F32) return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step needs FP32 moments");
+  if (static_cast<const void*>(lam_prev) == static_cast<const void*>(lam_next) ||
+      static_cast<const void*>(lam_prev) == static_cast<const void*>(m_t))
+    return fail(c, LBM_ERR_INVALID_ARG, "lam_prev must not alias lam_next or m_t");
+  if (!c->list_built) {
+    const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  hipError_t e = hipSuccess;
+  const int count = int(c->n_fluid_b + c->n_solid_b);
+  if (!c->flags_valid) {
+    if (!c->d_flags) e = hipMalloc(&c->d_flags, size_t(c->N));
+    if (e == hipSuccess) e = launch_adjoint_flags(c->d_mask, c->N, c->d_cells, c->d_bits, count, c->d_flags, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint flags");
+    c->flags_valid = true;
+  }
+  AdjParams p{};
+  const size_t P = size_t(c->N);
+  for (int k = 0; k < 10; ++k) {
+    p.lam_in[k] = lam_next + k * P;
+    p.m[k] = m_t + k * P;
+    p.lam_out[k] = lam_prev + k * P;
+  }
+  p.flags = c->d_flags;
+  p.g = geom(c);
+  p.om1 = float(1.0 - 1.0 / c->tau);
+  for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
+  e = launch_adjoint(p, c->d_cells, c->d_bits, count, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+  return LBM_OK;
+}
+
+int lbm_equilibrium_vjp(lbm_ctx* c, const float* rho, const float* u, const float* lam, float* grad_rho,
+                        float* grad_u) {
+  if (!c || !rho || !u || !lam || !grad_u) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  const hipError_t e = launch_equilibrium_vjp(rho, u, lam, c->d_mask, c->N, grad_rho, grad_u, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "equilibrium vjp");
   return LBM_OK;
 }
 

@@ -88,28 +88,10 @@ __device__ inline void store_cell_b(const StepParams& a, uint32_t cell, float dr
 #pragma unroll
     for (int k = 0; k < 10; ++k) *reinterpret_cast<float*>(static_cast<char*>(a.out[k]) + off) = v[k];
   } else {
-    const float rho = 1.0f + dr;
-    const float inv = 1.0f / rho;
-    const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
-    const float N[6] = {fmaf(-j[0], u[0], P[0]), fmaf(-j[1], u[1], P[1]), fmaf(-j[2], u[2], P[2]),
-                        fmaf(-j[0], u[1], P[3]), fmaf(-j[0], u[2], P[4]), fmaf(-j[1], u[2], P[5])};
-    uint32_t h1 = 0, h2 = 0;
-    const bool dith = a.dither != 0;
-    if (dith) dither_words(cell, a.key, h1, h2);
-    uint32_t q[10];
-    q[0] = quantize(dr - Q_DRHO_LO, Q_RHO_S, half_plus_xi<0>(h1, h2, dith));
-    q[1] = quantize(u[0] - Q_U_LO, Q_U_S, half_plus_xi<1>(h1, h2, dith));
-    q[2] = quantize(u[1] - Q_U_LO, Q_U_S, half_plus_xi<2>(h1, h2, dith));
-    q[3] = quantize(u[2] - Q_U_LO, Q_U_S, half_plus_xi<3>(h1, h2, dith));
-    q[4] = quantize(N[0] - Q_N_LO, Q_N_S, half_plus_xi<4>(h1, h2, dith));
-    q[5] = quantize(N[1] - Q_N_LO, Q_N_S, half_plus_xi<5>(h1, h2, dith));
-    q[6] = quantize(N[2] - Q_N_LO, Q_N_S, half_plus_xi<6>(h1, h2, dith));
-    q[7] = quantize(N[3] - Q_N_LO, Q_N_S, half_plus_xi<7>(h1, h2, dith));
-    q[8] = quantize(N[4] - Q_N_LO, Q_N_S, half_plus_xi<8>(h1, h2, dith));
-    q[9] = quantize(N[5] - Q_N_LO, Q_N_S, half_plus_xi<9>(h1, h2, dith));
+    uint32_t w[5];
+    encode_cell(dr, j, P, cell, a.key, a.dither != 0, w);
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
-      *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = q[2 * k] | (q[2 * k + 1] << 16);
+    for (int k = 0; k < 5; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
   }
 }
 

@@ -64,13 +64,13 @@ __device__ inline void dither_words(uint32_t idx, uint32_t key, uint32_t& h1, ui
   h2 = pcg_hash(h1 ^ 0x9E3779B9u);
 }
 
-// 1/2 + xi for component k (or 1/2 without dither).
+// 1/2 + xi = (v + 1/2)/64 for component k, the 6-bit field v of the hash
+// words.  Without dither the words are 0 and base is 1/2, which gives 1/2.
 template <int K>
-__device__ inline float half_plus_xi(uint32_t h1, uint32_t h2, bool dith) {
-  if (!dith) return 0.5f;
+__device__ inline float half_plus_xi(uint32_t h1, uint32_t h2, float base) {
   const uint32_t src = (K < 5) ? h1 : h2;
   const uint32_t v = (src >> (6 * (K % 5))) & 63u;
-  return fmaf(float(v), 1.0f / 64.0f, 1.0f / 128.0f);
+  return fmaf(float(v), 1.0f / 64.0f, base);
 }
 
 // floor((m - lo) * s + (1/2 + xi)), saturated to [0, 65535].
@@ -98,7 +98,7 @@ __device__ inline CellIn cell_from_moments(const float m[10]) {
   c.j[0] = m[1];
   c.j[1] = m[2];
   c.j[2] = m[3];
-  const float inv = 1.0f / c.rho;
+  const float inv = __builtin_amdgcn_rcpf(c.rho);
   c.u[0] = m[1] * inv;
   c.u[1] = m[2] * inv;
   c.u[2] = m[3] * inv;
@@ -232,6 +232,203 @@ __device__ inline void proj2(float F0, float Fp, float Fm, float& o0, float& o1)
   o1 = Fp - Fm;
 }
 __device__ inline float proj1(float F0, float Fp, float Fm) { return F0 + (Fp + Fm); }
+
+// ------------------------------------------ transposed 1D passes (adjoint) ---
+// The adjoint of one 1D pass.  Given the adjoints g0, g1, g2 of the outputs
+// o0, o1, o2 at a cell, the adjoints of that cell's three arriving movers are
+//   G0 = g0 - R3 g2,  G+ = g0 + g1 + P3 g2,  G- = g0 - g1 + P3 g2;
+// the mover f+ leaving cell y arrives at y + 1, so its adjoint is G+(y + 1)
+// (and f-'s is G-(y - 1)); then the adjoints of the group's channels are
+//   i0 = C0 g_f0 + C6 (g_f+ + g_f-),  i1 = (g_f+ - g_f-)/2,  i2 = g_f+ + g_f- - 2 g_f0.
+__device__ inline void projT3(float g0, float g1, float g2, float& G0, float& Gp, float& Gm) {
+  G0 = fmaf(-R3, g2, g0);
+  const float t = fmaf(P3, g2, g0);
+  Gp = t + g1;
+  Gm = t - g1;
+}
+__device__ inline void projT2(float g0, float g1, float& G0, float& Gp, float& Gm) {
+  G0 = g0;
+  Gp = g0 + g1;
+  Gm = g0 - g1;
+}
+__device__ inline void projT1(float g0, float& G0, float& Gp, float& Gm) { G0 = Gp = Gm = g0; }
+__device__ inline void reconT3(float f0, float fp, float fm, float& i0, float& i1, float& i2) {
+  const float s = fp + fm;
+  i0 = fmaf(C6, s, C0 * f0);
+  i1 = 0.5f * (fp - fm);
+  i2 = fmaf(-2.0f, f0, s);
+}
+__device__ inline void reconT2(float f0, float fp, float fm, float& i0, float& i1) {
+  i0 = fmaf(C6, fp + fm, C0 * f0);
+  i1 = 0.5f * (fp - fm);
+}
+__device__ inline float reconT1(float f0, float fp, float fm) { return fmaf(C6, fp + fm, C0 * f0); }
+
+// Transpose of the per-cell map m -> A (FP32 state: m = (rho - 1, j, P)):
+// decode (u = j / rho, N = P - j u), App. A collision (Nn = om1 dev N), the
+// coefficients of hermite_coeffs.  gA: adjoints of the 17 coefficients;
+// g: adjoints of the ten stored moments (added to).  When `own_u` is false the
+// coefficients were built with a fixed velocity u_in and j_in = rho u_in (the
+// inflow links), so u enters only through Nn.
+struct CellLin {
+  float rho, inv, j[3], u[3], N[6], Nn[6], ucf[3];  // ucf: velocity used in the coefficients
+};
+
+__device__ inline CellLin cell_lin(const float m[10], float om1, const float* uin) {
+  CellLin c;
+  c.rho = 1.0f + m[0];
+  c.inv = __builtin_amdgcn_rcpf(c.rho);
+  for (int a = 0; a < 3; ++a) {
+    c.j[a] = m[1 + a];
+    c.u[a] = m[1 + a] * c.inv;
+  }
+  c.N[0] = fmaf(-c.j[0], c.u[0], m[4]);
+  c.N[1] = fmaf(-c.j[1], c.u[1], m[5]);
+  c.N[2] = fmaf(-c.j[2], c.u[2], m[6]);
+  c.N[3] = fmaf(-c.j[0], c.u[1], m[7]);
+  c.N[4] = fmaf(-c.j[0], c.u[2], m[8]);
+  c.N[5] = fmaf(-c.j[1], c.u[2], m[9]);
+  collide_neq(c.N, om1, c.Nn);
+  for (int a = 0; a < 3; ++a) c.ucf[a] = uin ? uin[a] : c.u[a];
+  return c;
+}
+
+__device__ inline void coeffs_T(const CellLin& c, float om1, const float gA[NA], bool own_u, float g[10]) {
+  const float* v = c.ucf;
+  float jc[3];  // momentum used in the coefficients
+  for (int a = 0; a < 3; ++a) jc[a] = own_u ? c.j[a] : c.rho * v[a];
+  const float hxx = 0.5f * fmaf(jc[0], v[0], c.Nn[0]);
+  const float hyy = 0.5f * fmaf(jc[1], v[1], c.Nn[1]);
+  const float hzz = 0.5f * fmaf(jc[2], v[2], c.Nn[2]);
+  const float xy = fmaf(jc[0], v[1], c.Nn[3]);
+  // second- and third-order coefficients
+  const float g_hxx = gA[A200] + gA[A210] * v[1] + gA[A201] * v[2];
+  const float g_hyy = gA[A020] + gA[A120] * v[0] + gA[A021] * v[2];
+  const float g_hzz = gA[A002] + gA[A102] * v[0] + gA[A012] * v[1];
+  const float g_xy = gA[A110] + gA[A111] * v[2];
+  const float g_xz = gA[A101];
+  const float g_yz = gA[A011];
+  float gNn[6];
+  gNn[0] = 0.5f * g_hxx;
+  gNn[1] = 0.5f * g_hyy;
+  gNn[2] = 0.5f * g_hzz;
+  gNn[3] = gA[A210] * v[0] + gA[A120] * v[1] + g_xy;
+  gNn[4] = gA[A201] * v[0] + gA[A102] * v[2] + gA[A111] * v[1] + g_xz;
+  gNn[5] = gA[A021] * v[1] + gA[A012] * v[2] + gA[A111] * v[0] + g_yz;
+  float gv[3], gjc[3];
+  gv[0] = gA[A210] * c.Nn[3] + gA[A120] * hyy + gA[A201] * c.Nn[4] + gA[A102] * hzz + gA[A111] * c.Nn[5] +
+          0.5f * g_hxx * jc[0];
+  gv[1] = gA[A210] * hxx + gA[A120] * c.Nn[3] + gA[A021] * c.Nn[5] + gA[A012] * hzz + gA[A111] * c.Nn[4] +
+          0.5f * g_hyy * jc[1] + g_xy * jc[0];
+  gv[2] = gA[A201] * hxx + gA[A102] * c.Nn[4] + gA[A021] * hyy + gA[A012] * c.Nn[5] + gA[A111] * xy +
+          0.5f * g_hzz * jc[2] + g_xz * jc[0] + g_yz * jc[1];
+  gjc[0] = gA[A100] + 0.5f * g_hxx * v[0] + g_xy * v[1] + g_xz * v[2];
+  gjc[1] = gA[A010] + 0.5f * g_hyy * v[1] + g_yz * v[2];
+  gjc[2] = gA[A001] + 0.5f * g_hzz * v[2];
+  // collision: Nn_k = om1 (N_k - trace/3) on the diagonal, om1 N_k off it
+  const float mean = (gNn[0] + gNn[1] + gNn[2]) * (1.0f / 3.0f);
+  float gN[6];
+  for (int k = 0; k < 3; ++k) gN[k] = om1 * (gNn[k] - mean);
+  for (int k = 3; k < 6; ++k) gN[k] = om1 * gNn[k];
+  // decode: N = P - j u (pairs xx yy zz xy xz yz)
+  float gj[3], gu[3];
+  gj[0] = -(gN[0] * c.u[0] + gN[3] * c.u[1] + gN[4] * c.u[2]);
+  gj[1] = -(gN[1] * c.u[1] + gN[5] * c.u[2]);
+  gj[2] = -(gN[2] * c.u[2]);
+  gu[0] = -(gN[0] * c.j[0]);
+  gu[1] = -(gN[1] * c.j[1] + gN[3] * c.j[0]);
+  gu[2] = -(gN[2] * c.j[2] + gN[4] * c.j[0] + gN[5] * c.j[1]);
+  float grho = 0.0f;
+  if (own_u) {
+    for (int a = 0; a < 3; ++a) {
+      gu[a] += gv[a];
+      gj[a] += gjc[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) grho = fmaf(gjc[a], v[a], grho);
+  }
+  // u = j / rho
+  float ginv = 0.0f;
+  for (int a = 0; a < 3; ++a) {
+    gj[a] = fmaf(gu[a], c.inv, gj[a]);
+    ginv = fmaf(gu[a], c.j[a], ginv);
+  }
+  grho = fmaf(-ginv * c.inv, c.inv, grho);
+  g[0] += gA[A000] + grho;
+  for (int a = 0; a < 3; ++a) g[1 + a] += gj[a];
+  for (int k = 0; k < 6; ++k) g[4 + k] += gN[k];
+}
+
+// ------------------------------------------------------------------ encode ---
+// New moments (dr = rho - 1, j, P) -> five code words: u = j / rho,
+// N = P - j u, each normalised, dithered, rounded and saturated (Sec. 5.3).
+//
+// v_cvt_pknorm_u16_f32 returns floor(clamp(x, 0, 1) * 65535 + 1/2) for every
+// float x (round to nearest; ties cannot occur because 65535 x + 1/2 is never
+// an integer for a binary x in (0, 1)), for two values at once.  With
+// x = (m - min)/(max - min) + xi/65535 it gives the paper's
+// q = floor(m' (2^16 - 1) + 1/2 + xi) including the saturation, from one fma
+// per value.
+#ifndef LBM_PKNORM_ENCODE
+#define LBM_PKNORM_ENCODE 1
+#endif
+constexpr float QN_RHO_S = float(1.0 / 0.7), QN_RHO_C = float(0.2 / 0.7);  // x = (rho - 1)/0.7 + 0.2/0.7
+constexpr float QN_U_S = float(1.0 / 0.8), QN_U_C = 0.5f;
+constexpr float QN_N_S = float(1.0 / 0.2), QN_N_C = 0.5f;
+constexpr float QN_LSB = float(1.0 / 65535.0);
+constexpr float QN_XI0 = float((1.0 / 128.0 - 0.5) / 65535.0);  // xi / 65535 at v = 0
+constexpr float QN_XIS = float(1.0 / (64.0 * 65535.0));          // per dither level
+
+typedef unsigned short lbm_ushort2 __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pknorm2(float lo, float hi) {
+  const lbm_ushort2 v = __builtin_amdgcn_cvt_pknorm_u16(lo, hi);
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// xi / 65535 + c for component k: v the 6-bit field of the hash words.
+template <int K>
+__device__ inline float xi_norm(uint32_t h1, uint32_t h2, float c) {
+  const uint32_t src = (K < 5) ? h1 : h2;
+  const uint32_t v = (src >> (6 * (K % 5))) & 63u;
+  return fmaf(float(v), QN_XIS, c);
+}
+
+__device__ inline void encode_cell(float dr, const float j[3], const float P[6], uint32_t cell, uint32_t key,
+                                   bool dith, uint32_t w[5]) {
+  const float inv = __builtin_amdgcn_rcpf(1.0f + dr);
+  const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
+  const float N[6] = {fmaf(-j[0], u[0], P[0]), fmaf(-j[1], u[1], P[1]), fmaf(-j[2], u[2], P[2]),
+                      fmaf(-j[0], u[1], P[3]), fmaf(-j[0], u[2], P[4]), fmaf(-j[1], u[2], P[5])};
+  uint32_t h1 = 0, h2 = 0;
+  if (dith) dither_words(cell, key, h1, h2);
+#if LBM_PKNORM_ENCODE
+  const float x0 = dith ? QN_XI0 : 0.0f;
+  const float cr = QN_RHO_C + x0, cu = QN_U_C + x0, cn = QN_N_C + x0;
+  w[0] = pknorm2(fmaf(dr, QN_RHO_S, xi_norm<0>(h1, h2, cr)), fmaf(u[0], QN_U_S, xi_norm<1>(h1, h2, cu)));
+  w[1] = pknorm2(fmaf(u[1], QN_U_S, xi_norm<2>(h1, h2, cu)), fmaf(u[2], QN_U_S, xi_norm<3>(h1, h2, cu)));
+  w[2] = pknorm2(fmaf(N[0], QN_N_S, xi_norm<4>(h1, h2, cn)), fmaf(N[1], QN_N_S, xi_norm<5>(h1, h2, cn)));
+  w[3] = pknorm2(fmaf(N[2], QN_N_S, xi_norm<6>(h1, h2, cn)), fmaf(N[3], QN_N_S, xi_norm<7>(h1, h2, cn)));
+  w[4] = pknorm2(fmaf(N[4], QN_N_S, xi_norm<8>(h1, h2, cn)), fmaf(N[5], QN_N_S, xi_norm<9>(h1, h2, cn)));
+#else
+  const float base = dith ? 1.0f / 128.0f : 0.5f;
+  const uint32_t q0 = quantize(dr - Q_DRHO_LO, Q_RHO_S, half_plus_xi<0>(h1, h2, base));
+  const uint32_t q1 = quantize(u[0] - Q_U_LO, Q_U_S, half_plus_xi<1>(h1, h2, base));
+  const uint32_t q2 = quantize(u[1] - Q_U_LO, Q_U_S, half_plus_xi<2>(h1, h2, base));
+  const uint32_t q3 = quantize(u[2] - Q_U_LO, Q_U_S, half_plus_xi<3>(h1, h2, base));
+  const uint32_t q4 = quantize(N[0] - Q_N_LO, Q_N_S, half_plus_xi<4>(h1, h2, base));
+  const uint32_t q5 = quantize(N[1] - Q_N_LO, Q_N_S, half_plus_xi<5>(h1, h2, base));
+  const uint32_t q6 = quantize(N[2] - Q_N_LO, Q_N_S, half_plus_xi<6>(h1, h2, base));
+  const uint32_t q7 = quantize(N[3] - Q_N_LO, Q_N_S, half_plus_xi<7>(h1, h2, base));
+  const uint32_t q8 = quantize(N[4] - Q_N_LO, Q_N_S, half_plus_xi<8>(h1, h2, base));
+  const uint32_t q9 = quantize(N[5] - Q_N_LO, Q_N_S, half_plus_xi<9>(h1, h2, base));
+  w[0] = q0 | (q1 << 16);
+  w[1] = q2 | (q3 << 16);
+  w[2] = q4 | (q5 << 16);
+  w[3] = q6 | (q7 << 16);
+  w[4] = q8 | (q9 << 16);
+#endif
+}
 
 // ------------------------------------------------------------ int helpers ---
 __device__ inline int wrapi(int v, int n) {

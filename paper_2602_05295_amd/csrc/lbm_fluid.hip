@@ -1,38 +1,80 @@
 // lbm_fluid.hip -- the fused fluid pass (Sec. 4.2, Alg. 2) for gfx950.
 //
-// One workgroup owns an x-y tile of (FTX-2) x (FTY-2) output cells plus a
-// one-cell halo ring, and marches through a chunk of z planes.  Per plane each
-// thread loads its cell's moments once (coalesced along x), collides in moment
-// space (App. A) and forms the 17 Hermite coefficients; then
-//   x pass: reconstruct the x-directional distributions of 8 groups, exchange
-//           the +x / -x movers with the x neighbours through LDS, project;
-//   y pass: the same on 9 groups with the y neighbours;
-//   z pass: the same on 6 groups, with the z neighbours held in registers
-//           from the previous planes of the march (no exchange at all).
-// Only the ten new moments are written, so a cell's state crosses HBM once in
-// and once out per step.  Every axis is treated as periodic here; faces and
-// walls are overwritten afterwards by the boundary pass.
+// The step factorises into three 1D "reconstruct -> shift -> project" passes
+// (lbm_device.h).  One workgroup of 16 wavefronts owns a tile of 64 x 13
+// output cells of an x-y plane and marches through z:
+//   - 15 row wavefronts: one 64-cell row each (a coalesced 256 B or 128 B
+//     row per plane), the 13 output rows plus one halo row above and below;
+//   - 1 column wavefront: the halo cells at x0 - 1 and x0 + 64 of those 15
+//     rows, so no lane of the row wavefronts is spent on halo cells.
+// Per plane every cell is loaded once and collided (App. A); then
+//   y pass: reconstruct the y movers of 8 groups, exchange them through LDS
+//           (the halo rows stop here, having paid for a load, a collision and
+//           this reconstruction only);
+//   x pass: the same on 9 groups through LDS, the column wavefront supplying
+//           the movers that enter the tile from outside;
+//   z pass: 6 groups whose z neighbours are the previous and next planes of
+//           the march, held in registers.
+// Only the ten new moments are written.  The next plane's state is loaded
+// while the current one is computed.
+//
+// The grid is persistent: every workgroup takes an equal contiguous range of
+// the (tile, z) work list, tile-major, so it marches one or two z segments;
+// workgroups on the same XCD (round-robin dispatch) get neighbouring ranges so
+// that halo re-reads stay in that XCD's L2.  Every axis is treated as periodic
+// here; faces and walls are overwritten afterwards by the boundary pass.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
 namespace lbm {
 
-constexpr int FTX = 32;  // threads along x (30 outputs)
-constexpr int FTY = 16;  // threads along y (14 outputs)
+#ifndef LBM_TILE_ROWS
+#define LBM_TILE_ROWS 13
+#endif
+#ifndef LBM_PREFETCH
+#define LBM_PREFETCH 1
+#endif
+constexpr int RW = 64;               // cells per row wavefront
+constexpr int TYR = LBM_TILE_ROWS;   // output rows per tile
+constexpr int NRW = TYR + 2;         // row wavefronts (with the two halo rows)
+constexpr int NTH = (NRW + 1) * RW;  // plus the halo-column wavefront
+
+struct FluidLds {
+  float ly[16][NRW][RW];      // y movers (+, -) of 8 groups, row wavefronts
+  float lyc[16][2][16];       // y movers of the two halo columns
+  float lx[18][TYR][RW + 2];  // x movers (+, -) of 9 groups, with halo columns at 0 and RW + 1
+};
 
 template <int FMT>
-__device__ inline CellIn load_cell(const StepParams& a, uint32_t off) {
+struct Raw;
+template <>
+struct Raw<FMT_F32> {
+  float v[10];
+};
+template <>
+struct Raw<FMT_Q16> {
+  uint32_t v[5];
+};
+
+template <int FMT>
+__device__ inline Raw<FMT> load_raw(const StepParams& a, uint32_t off) {
+  Raw<FMT> r;
   if constexpr (FMT == FMT_F32) {
-    float m[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) m[k] = *reinterpret_cast<const float*>(static_cast<const char*>(a.in[k]) + off);
-    return cell_from_moments(m);
+    for (int k = 0; k < 10; ++k) r.v[k] = *reinterpret_cast<const float*>(static_cast<const char*>(a.in[k]) + off);
   } else {
-    uint32_t w[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) w[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + off);
-    return cell_from_words(w);
+    for (int k = 0; k < 5; ++k) r.v[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + off);
   }
+  return r;
+}
+
+template <int FMT>
+__device__ inline CellIn decode(const Raw<FMT>& r) {
+  if constexpr (FMT == FMT_F32)
+    return cell_from_moments(r.v);
+  else
+    return cell_from_words(r.v);
 }
 
 // Writes the new moments of one cell: dr = rho - 1, j, P (xx yy zz xy xz yz).
@@ -44,159 +86,218 @@ __device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, 
 #pragma unroll
     for (int k = 0; k < 10; ++k) *reinterpret_cast<float*>(static_cast<char*>(a.out[k]) + off) = v[k];
   } else {
-    const float rho = 1.0f + dr;
-    const float inv = 1.0f / rho;
-    const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
-    const float N[6] = {fmaf(-j[0], u[0], P[0]), fmaf(-j[1], u[1], P[1]), fmaf(-j[2], u[2], P[2]),
-                        fmaf(-j[0], u[1], P[3]), fmaf(-j[0], u[2], P[4]), fmaf(-j[1], u[2], P[5])};
-    uint32_t h1 = 0, h2 = 0;
-    const bool dith = a.dither != 0;
-    if (dith) dither_words(cell, a.key, h1, h2);
-    const uint32_t q0 = quantize(dr - Q_DRHO_LO, Q_RHO_S, half_plus_xi<0>(h1, h2, dith));
-    const uint32_t q1 = quantize(u[0] - Q_U_LO, Q_U_S, half_plus_xi<1>(h1, h2, dith));
-    const uint32_t q2 = quantize(u[1] - Q_U_LO, Q_U_S, half_plus_xi<2>(h1, h2, dith));
-    const uint32_t q3 = quantize(u[2] - Q_U_LO, Q_U_S, half_plus_xi<3>(h1, h2, dith));
-    const uint32_t q4 = quantize(N[0] - Q_N_LO, Q_N_S, half_plus_xi<4>(h1, h2, dith));
-    const uint32_t q5 = quantize(N[1] - Q_N_LO, Q_N_S, half_plus_xi<5>(h1, h2, dith));
-    const uint32_t q6 = quantize(N[2] - Q_N_LO, Q_N_S, half_plus_xi<6>(h1, h2, dith));
-    const uint32_t q7 = quantize(N[3] - Q_N_LO, Q_N_S, half_plus_xi<7>(h1, h2, dith));
-    const uint32_t q8 = quantize(N[4] - Q_N_LO, Q_N_S, half_plus_xi<8>(h1, h2, dith));
-    const uint32_t q9 = quantize(N[5] - Q_N_LO, Q_N_S, half_plus_xi<9>(h1, h2, dith));
-    *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[0]) + off) = q0 | (q1 << 16);
-    *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[1]) + off) = q2 | (q3 << 16);
-    *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[2]) + off) = q4 | (q5 << 16);
-    *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[3]) + off) = q6 | (q7 << 16);
-    *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[4]) + off) = q8 | (q9 << 16);
+    uint32_t w[5];
+    encode_cell(dr, j, P, cell, a.key, a.dither != 0, w);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
   }
 }
+
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 template <int FMT>
-__global__ void __launch_bounds__(FTX* FTY) fluid_kernel(StepParams a) {
-  __shared__ float lx[16][FTY][FTX];  // x movers: (+, -) of 8 groups
-  __shared__ float ly[18][FTY][FTX];  // y movers: (+, -) of 9 groups
+__global__ void __launch_bounds__(NTH) fluid_kernel(StepParams a, int ntx, int nty, int nwg) {
+  __shared__ FluidLds L;
 
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int gx = int(blockIdx.x) * (FTX - 2) - 1 + tx;
-  const int gy = int(blockIdx.y) * (FTY - 2) - 1 + ty;
-  const int xw = wrapi(gx, nx), yw = wrapi(gy, ny);
-  const bool own = tx >= 1 && tx <= FTX - 2 && ty >= 1 && ty <= FTY - 2 && gx < nx && gy < ny;
-  const int txm = tx > 0 ? tx - 1 : 0, txp = tx < FTX - 1 ? tx + 1 : FTX - 1;
-  const int tym = ty > 0 ? ty - 1 : 0, typ = ty < FTY - 1 ? ty + 1 : FTY - 1;
-  const int z0 = int(blockIdx.z) * a.zchunk;
-  const int z1 = min(z0 + a.zchunk, nz);
+  const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
+  const bool colw = wave == NRW;
+  int r, dx, side = 0;
+  bool active = true;
+  if (!colw) {
+    r = wave;
+    dx = lane;
+  } else {
+    side = lane >> 5;
+    r = lane & 31;
+    active = r < NRW;
+    if (!active) r = NRW - 1;
+    dx = side ? RW : -1;
+  }
+  const bool inner = r >= 1 && r <= TYR;  // a row whose y and x passes are needed
+  const bool compute = !colw && inner;    // a row wavefront with outputs
+
+  // this workgroup's range of the (tile, z) work list; XCD-grouped
+  const int b = int(blockIdx.x);
+  const int lb = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
+  const uint64_t W = uint64_t(ntx) * uint64_t(nty) * uint64_t(nz);
+  uint64_t w = W * uint64_t(lb) / uint64_t(nwg);
+  const uint64_t wend = W * uint64_t(lb + 1) / uint64_t(nwg);
   const uint32_t plane = uint32_t(nx) * uint32_t(ny);
-  const uint32_t row = uint32_t(xw) + uint32_t(nx) * uint32_t(yw);
 
-  // z window: f+ of the plane two back, f+ and f0 of the previous plane
-  float wp2[6], wp1[6], w0[6];
-#pragma unroll
-  for (int g = 0; g < 6; ++g) wp2[g] = wp1[g] = w0[g] = 0.0f;
+  while (w < wend) {
+    const int t = int(w / uint64_t(nz));
+    const int za = int(w % uint64_t(nz));
+    const int zb = int(min(uint64_t(nz), uint64_t(za) + (wend - w)));
+    w += uint64_t(zb - za);
+    const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
+    const int gx = x0 + dx, gy = y0 - 1 + r;
+    const int xw = wrapi(gx, nx), yw = wrapi(gy, ny);
+    const uint32_t row = uint32_t(xw) + uint32_t(nx) * uint32_t(yw);
+    const bool own = compute && gx < nx && gy < ny;
 
-  for (int p = z0 - 1; p <= z1; ++p) {
-    const int zw = wrapi(p, nz);
-    const uint32_t cell = row + plane * uint32_t(zw);
-    const CellIn c = load_cell<FMT>(a, cell * 4u);
-    float Nn[6];
-    collide_neq(c.N, a.om1, Nn);
-    float A[NA];
-    hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+    float wp2[6], wp1[6], w0[6];
+#pragma unroll
+    for (int g = 0; g < 6; ++g) wp2[g] = wp1[g] = w0[g] = 0.0f;
 
-    // ---- x pass: groups (m, l) with inputs n = 0, 1, 2 along x
-    float f0[8], fp[8], fm[8];
-    recon3(A[A000], A[A100], A[A200], f0[0], fp[0], fm[0]);  // (0,0)
-    recon3(A[A010], A[A110], A[A210], f0[1], fp[1], fm[1]);  // (1,0)
-    recon3(A[A001], A[A101], A[A201], f0[2], fp[2], fm[2]);  // (0,1)
-    recon2(A[A020], A[A120], f0[3], fp[3], fm[3]);           // (2,0)
-    recon2(A[A002], A[A102], f0[4], fp[4], fm[4]);           // (0,2)
-    recon2(A[A011], A[A111], f0[5], fp[5], fm[5]);           // (1,1)
-    recon1(A[A021], f0[6], fp[6], fm[6]);                    // (2,1)
-    recon1(A[A012], f0[7], fp[7], fm[7]);                    // (1,2)
-#pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      lx[2 * g][ty][tx] = fp[g];
-      lx[2 * g + 1][ty][tx] = fm[g];
-    }
-    __syncthreads();
-    float X[8][3];  // X[g][a] = channel (a, m, l)
-#pragma unroll
-    for (int g = 0; g < 8; ++g) proj3(f0[g], lx[2 * g][ty][txm], lx[2 * g + 1][ty][txp], X[g][0], X[g][1], X[g][2]);
+#if LBM_PREFETCH >= 2
+    // two planes in flight ahead of the one being computed
+    Raw<FMT> nxt1 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za - 1, nz))) * 4u);
+    Raw<FMT> nxt2 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za, nz))) * 4u);
+    for (int p = za - 1; p <= zb; ++p) {
+      const Raw<FMT> cur = nxt1;
+      nxt1 = nxt2;
+      if (p + 2 <= zb) nxt2 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 2, nz))) * 4u);
+#else
+    // the next plane in flight while the current one is computed
+    Raw<FMT> nxt1 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za - 1, nz))) * 4u);
+    for (int p = za - 1; p <= zb; ++p) {
+      const Raw<FMT> cur = nxt1;
+      if (p + 1 <= zb) nxt1 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
+#endif
 
-    // ---- y pass: groups (a, l) with inputs m = 0, 1, 2 along y
-    float y0[9], yp[9], ym[9];
-#pragma unroll
-    for (int a3 = 0; a3 < 3; ++a3) {
-      recon3(X[0][a3], X[1][a3], X[3][a3], y0[3 * a3 + 0], yp[3 * a3 + 0], ym[3 * a3 + 0]);  // l = 0
-      recon3(X[2][a3], X[5][a3], X[6][a3], y0[3 * a3 + 1], yp[3 * a3 + 1], ym[3 * a3 + 1]);  // l = 1
-      recon2(X[4][a3], X[7][a3], y0[3 * a3 + 2], yp[3 * a3 + 2], ym[3 * a3 + 2]);            // l = 2
-    }
-#pragma unroll
-    for (int h = 0; h < 9; ++h) {
-      ly[2 * h][ty][tx] = yp[h];
-      ly[2 * h + 1][ty][tx] = ym[h];
-    }
-    __syncthreads();
-    float Y00[3], Y01[3], Y02[3], Y10[3], Y11[3], Y20[3];  // Yab[l] = channel (a, b, l)
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      proj3(y0[l], ly[2 * l][tym][tx], ly[2 * l + 1][typ][tx], Y00[l], Y01[l], Y02[l]);
-      proj2(y0[3 + l], ly[2 * (3 + l)][tym][tx], ly[2 * (3 + l) + 1][typ][tx], Y10[l], Y11[l]);
-      Y20[l] = proj1(y0[6 + l], ly[2 * (6 + l)][tym][tx], ly[2 * (6 + l) + 1][typ][tx]);
-    }
+      const CellIn c = decode<FMT>(cur);
+      float Nn[6];
+      collide_neq(c.N, a.om1, Nn);
+      float A[NA];
+      hermite_coeffs(c.dr, c.j, c.u, Nn, A);
 
-    // ---- z pass: groups (a, b) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2), inputs l = 0, 1, 2
-    float zf0[6], zfp[6], zfm[6];
-    recon3(Y00[0], Y00[1], Y00[2], zf0[0], zfp[0], zfm[0]);
-    recon3(Y10[0], Y10[1], Y10[2], zf0[1], zfp[1], zfm[1]);
-    recon3(Y01[0], Y01[1], Y01[2], zf0[2], zfp[2], zfm[2]);
-    recon3(Y20[0], Y20[1], Y20[2], zf0[3], zfp[3], zfm[3]);
-    recon3(Y11[0], Y11[1], Y11[2], zf0[4], zfp[4], zfm[4]);
-    recon3(Y02[0], Y02[1], Y02[2], zf0[5], zfp[5], zfm[5]);
-
-    if (p > z0) {  // plane q = p - 1 is complete
-      float dr, j[3], P[6];
-      proj3(w0[0], wp2[0], zfm[0], dr, j[2], P[2]);  // (0,0,c): rho-1, jz, Pzz
-      proj2(w0[1], wp2[1], zfm[1], j[0], P[4]);      // (1,0,c): jx, Pxz
-      proj2(w0[2], wp2[2], zfm[2], j[1], P[5]);      // (0,1,c): jy, Pyz
-      P[0] = proj1(w0[3], wp2[3], zfm[3]);           // Pxx
-      P[3] = proj1(w0[4], wp2[4], zfm[4]);           // Pxy
-      P[1] = proj1(w0[5], wp2[5], zfm[5]);           // Pyy
-      if (own) store_cell<FMT>(a, row + plane * uint32_t(p - 1), dr, j, P);
-    }
+      // ---- y pass: groups (n, l) with inputs m = 0, 1, 2 along y
+      float f0[8], fp[8], fm[8];
+      recon3(A[A000], A[A010], A[A020], f0[0], fp[0], fm[0]);  // (0,0)
+      recon3(A[A100], A[A110], A[A120], f0[1], fp[1], fm[1]);  // (1,0)
+      recon3(A[A001], A[A011], A[A021], f0[2], fp[2], fm[2]);  // (0,1)
+      recon2(A[A200], A[A210], f0[3], fp[3], fm[3]);           // (2,0)
+      recon2(A[A002], A[A012], f0[4], fp[4], fm[4]);           // (0,2)
+      recon2(A[A101], A[A111], f0[5], fp[5], fm[5]);           // (1,1)
+      recon1(A[A201], f0[6], fp[6], fm[6]);                    // (2,1)
+      recon1(A[A102], f0[7], fp[7], fm[7]);                    // (1,2)
+      if (!colw) {
 #pragma unroll
-    for (int g = 0; g < 6; ++g) {
-      wp2[g] = wp1[g];
-      wp1[g] = zfp[g];
-      w0[g] = zf0[g];
+        for (int g = 0; g < 8; ++g) {
+          L.ly[2 * g][r][lane] = fp[g];
+          L.ly[2 * g + 1][r][lane] = fm[g];
+        }
+      } else if (active) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          L.lyc[2 * g][side][r] = fp[g];
+          L.lyc[2 * g + 1][side][r] = fm[g];
+        }
+      }
+      __syncthreads();
+
+      float Y[8][3];  // Y[g][b] = channel (n, b, l) of y-group g = (n, l)
+      float x0v[9], xp[9], xm[9];
+      if (inner) {
+        if (!colw) {
+#pragma unroll
+          for (int g = 0; g < 8; ++g)
+            proj3(f0[g], L.ly[2 * g][r - 1][lane], L.ly[2 * g + 1][r + 1][lane], Y[g][0], Y[g][1], Y[g][2]);
+        } else {
+#pragma unroll
+          for (int g = 0; g < 8; ++g)
+            proj3(f0[g], L.lyc[2 * g][side][r - 1], L.lyc[2 * g + 1][side][r + 1], Y[g][0], Y[g][1], Y[g][2]);
+        }
+        // ---- x pass: groups (b, l) with inputs n = 0, 1, 2 along x
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          recon3(Y[0][bb], Y[1][bb], Y[3][bb], x0v[3 * bb + 0], xp[3 * bb + 0], xm[3 * bb + 0]);  // l = 0
+          recon3(Y[2][bb], Y[5][bb], Y[6][bb], x0v[3 * bb + 1], xp[3 * bb + 1], xm[3 * bb + 1]);  // l = 1
+          recon2(Y[4][bb], Y[7][bb], x0v[3 * bb + 2], xp[3 * bb + 2], xm[3 * bb + 2]);            // l = 2
+        }
+        if (!colw) {
+#pragma unroll
+          for (int h = 0; h < 9; ++h) {
+            L.lx[2 * h][r - 1][lane + 1] = xp[h];
+            L.lx[2 * h + 1][r - 1][lane + 1] = xm[h];
+          }
+        } else if (active) {
+          if (side == 0) {
+#pragma unroll
+            for (int h = 0; h < 9; ++h) L.lx[2 * h][r - 1][0] = xp[h];
+          } else {
+#pragma unroll
+            for (int h = 0; h < 9; ++h) L.lx[2 * h + 1][r - 1][RW + 1] = xm[h];
+          }
+        }
+      }
+      __syncthreads();
+
+      if (compute) {
+        float X00[3], X10[3], X20[3], X01[3], X11[3], X02[3];  // Xab[l] = channel (a, b, l)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          proj3(x0v[l], L.lx[2 * l][r - 1][lane], L.lx[2 * l + 1][r - 1][lane + 2], X00[l], X10[l], X20[l]);
+          proj2(x0v[3 + l], L.lx[2 * (3 + l)][r - 1][lane], L.lx[2 * (3 + l) + 1][r - 1][lane + 2], X01[l], X11[l]);
+          X02[l] = proj1(x0v[6 + l], L.lx[2 * (6 + l)][r - 1][lane], L.lx[2 * (6 + l) + 1][r - 1][lane + 2]);
+        }
+        // ---- z pass: groups (a, b) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2), inputs l = 0, 1, 2
+        float zf0[6], zfp[6], zfm[6];
+        recon3(X00[0], X00[1], X00[2], zf0[0], zfp[0], zfm[0]);
+        recon3(X10[0], X10[1], X10[2], zf0[1], zfp[1], zfm[1]);
+        recon3(X01[0], X01[1], X01[2], zf0[2], zfp[2], zfm[2]);
+        recon3(X20[0], X20[1], X20[2], zf0[3], zfp[3], zfm[3]);
+        recon3(X11[0], X11[1], X11[2], zf0[4], zfp[4], zfm[4]);
+        recon3(X02[0], X02[1], X02[2], zf0[5], zfp[5], zfm[5]);
+        if (p > za) {  // plane p - 1 is complete
+          float dr, j[3], P[6];
+          proj3(w0[0], wp2[0], zfm[0], dr, j[2], P[2]);  // (0,0,c): rho-1, jz, Pzz
+          proj2(w0[1], wp2[1], zfm[1], j[0], P[4]);      // (1,0,c): jx, Pxz
+          proj2(w0[2], wp2[2], zfm[2], j[1], P[5]);      // (0,1,c): jy, Pyz
+          P[0] = proj1(w0[3], wp2[3], zfm[3]);           // Pxx
+          P[3] = proj1(w0[4], wp2[4], zfm[4]);           // Pxy
+          P[1] = proj1(w0[5], wp2[5], zfm[5]);           // Pyy
+          if (own) store_cell<FMT>(a, row + plane * uint32_t(p - 1), dr, j, P);
+        }
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+          wp2[g] = wp1[g];
+          wp1[g] = zfp[g];
+          w0[g] = zf0[g];
+        }
+      }
     }
   }
 }
 
-void fluid_tiling(const Geometry& g, dim3* grid, dim3* block, int* zchunk) {
-  const int ntx = (g.nx + FTX - 3) / (FTX - 2);
-  const int nty = (g.ny + FTY - 3) / (FTY - 2);
-  const int tiles = ntx * nty;
-  int chunks = (2048 + tiles - 1) / tiles;
-  const int maxchunks = (g.nz + 7) / 8;
-  if (chunks > maxchunks) chunks = maxchunks;
-  if (chunks < 1) chunks = 1;
-  int zc = (g.nz + chunks - 1) / chunks;
-  chunks = (g.nz + zc - 1) / zc;
-  *grid = dim3(ntx, nty, chunks);
-  *block = dim3(FTX, FTY, 1);
-  *zchunk = zc;
+namespace {
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+}  // namespace
+
+void fluid_tiling(const Geometry& g, dim3* grid, dim3* block, int* ntx, int* nty, int* nwg) {
+  *ntx = (g.nx + RW - 1) / RW;
+  *nty = (g.ny + TYR - 1) / TYR;
+  const uint64_t W = uint64_t(*ntx) * uint64_t(*nty) * uint64_t(g.nz);
+  // one workgroup per CU (it takes 1024 threads and ~122 KB of LDS); at least
+  // ~8 planes of work per workgroup
+  uint64_t n = uint64_t(device_cus());
+  const uint64_t cap = (W + 7) / 8;
+  if (n > cap) n = cap;
+  if (n < 1) n = 1;
+  *nwg = int(n);
+  *grid = dim3(uint32_t(n));
+  *block = dim3(NTH);
 }
 
 hipError_t launch_fluid(int fmt, const StepParams& p, hipStream_t s) {
   dim3 grid, block;
-  int zc;
-  fluid_tiling(p.g, &grid, &block, &zc);
-  StepParams q = p;
-  q.zchunk = zc;
+  int ntx, nty, nwg;
+  fluid_tiling(p.g, &grid, &block, &ntx, &nty, &nwg);
   if (fmt == FMT_F32)
-    hipLaunchKernelGGL(fluid_kernel<FMT_F32>, grid, block, 0, s, q);
+    hipLaunchKernelGGL(fluid_kernel<FMT_F32>, grid, block, 0, s, p, ntx, nty, nwg);
   else
-    hipLaunchKernelGGL(fluid_kernel<FMT_Q16>, grid, block, 0, s, q);
+    hipLaunchKernelGGL(fluid_kernel<FMT_Q16>, grid, block, 0, s, p, ntx, nty, nwg);
   return hipGetLastError();
 }
 

@@ -22,16 +22,30 @@ struct StepParams {
   const void* in[10];  // state planes read (FP32: 10 float planes, Q16: 5 word planes)
   void* out[10];       // state planes written
   Geometry g;
-  int zchunk;
   float om1;           // 1 - 1/tau
   uint32_t key;        // dither key of this step
   int dither;          // 0: round to nearest; else add the dither of `key`
   float u_in[3];
 };
 
+// Adjoint of one FP32 step: lam_out = J(m)^T lam_in.
+struct AdjParams {
+  const float* lam_in[10];  // adjoint of the new moments (10 planes, moment order)
+  const float* m[10];       // forward FP32 state (rho - 1, j, P) the step was taken from
+  float* lam_out[10];       // adjoint of the old moments
+  const uint8_t* flags;     // 1: listed fluid cell, 2: solid cell, 0: other
+  Geometry g;
+  float om1;
+  float u_in[3];
+};
+hipError_t launch_adjoint(const AdjParams& p, const uint32_t* cells, const uint32_t* bits, int count, hipStream_t s);
+hipError_t launch_adjoint_flags(const uint8_t* mask, int64_t N, const uint32_t* cells, const uint32_t* bits,
+                                int count, uint8_t* flags, hipStream_t s);
+hipError_t launch_equilibrium_vjp(const float* rho, const float* u, const float* lam, const uint8_t* mask, int64_t N,
+                                  float* grho, float* gu, hipStream_t s);
+
 // Fused fluid pass over every cell (all axes treated periodic).
 hipError_t launch_fluid(int fmt, const StepParams& p, hipStream_t s);
-void fluid_tiling(const Geometry& g, dim3* grid, dim3* block, int* zchunk);
 
 // Boundary pass over the compacted list.
 hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits, int count,

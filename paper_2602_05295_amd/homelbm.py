@@ -85,6 +85,8 @@ def lib():
     L.lbm_synchronize.argtypes = [vp]
     L.lbm_profile_steps.argtypes = [vp, i, P(ctypes.c_double), P(ctypes.c_double), P(i), P(i)]
     L.lbm_debug_dither.argtypes = [i, vp, ctypes.c_uint32, ctypes.c_uint32, i, vp]
+    L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
+    L.lbm_equilibrium_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -265,6 +267,29 @@ class HomeLBM:
         if st not in (OK, ERR_UNSTABLE):
             self._check(st)
         return bad.value
+
+    # -- adjoint (FP32 contexts; torch CUDA tensors)
+    def adjoint_step(self, m_t, lam_next, lam_prev):
+        """lam_prev <- J(m_t)^T lam_next; m_t is a raw FP32 state (get_raw layout)."""
+        n = 10 * self.N
+        p1, d1, k1 = _ptr(m_t, np.float32, n)
+        p2, d2, k2 = _ptr(lam_next, np.float32, n)
+        p3, d3, k3 = _ptr(lam_prev, np.float32, n)
+        if not (d1 and d2 and d3):
+            raise ValueError("adjoint_step takes device tensors")
+        self._check(lib().lbm_adjoint_step(self._h, p1, p2, p3))
+
+    def equilibrium_vjp(self, rho, u, lam, grad_u, grad_rho=None):
+        p1, d1, k1 = _ptr(rho, np.float32, self.N)
+        p2, d2, k2 = _ptr(u, np.float32, 3 * self.N)
+        p3, d3, k3 = _ptr(lam, np.float32, 10 * self.N)
+        p4, d4, k4 = _ptr(grad_u, np.float32, 3 * self.N)
+        p5 = None
+        if grad_rho is not None:
+            p5, d5, k5 = _ptr(grad_rho, np.float32, self.N)
+        if not (d1 and d2 and d3 and d4):
+            raise ValueError("equilibrium_vjp takes device tensors")
+        self._check(lib().lbm_equilibrium_vjp(self._h, p1, p2, p3, p5, p4))
 
     def profile_steps(self, n):
         """Runs n steps with per-kernel HIP events: dict of summed ms and launch counts."""
