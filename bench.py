@@ -206,6 +206,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--formats", default="q16,fp32", help="storage formats to run (the headline value is q16)")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint ratio and the channel run")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB three times (the reference kernel that "
+                         "scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path; "
@@ -215,6 +218,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {nbytes} bytes", file=sys.stderr, flush=True)
+        del src, dst
     print(f"[bench] device {torch.cuda.get_device_name(0)}; building the {N}^3 field", file=sys.stderr, flush=True)
     rho, u = workload()
     rho_d = torch.from_numpy(rho).cuda()

@@ -237,9 +237,10 @@ def adjoint_step(params: Params, m_t, lam_next, mask=None):
 
 def equilibrium_moments(rho, u):
     """Initial state from (rho, u): j = rho u, P = rho u u (no non-equilibrium part)."""
-    rho = np.asarray(rho, dtype=np.float64)
-    u = np.asarray(u, dtype=np.float64)
-    m = np.zeros((10,) + rho.shape)
+    dt = np.result_type(np.asarray(rho), np.asarray(u), np.float64)  # complex stays complex
+    rho = np.asarray(rho, dtype=dt)
+    u = np.asarray(u, dtype=dt)
+    m = np.zeros((10,) + rho.shape, dtype=dt)
     m[0] = rho
     for a in range(3):
         m[1 + a] = rho * u[a]

@@ -1,10 +1,10 @@
 // lbm_fluid.hip -- the fused fluid pass (Sec. 4.2, Alg. 2) for gfx950.
 //
 // The step factorises into three 1D "reconstruct -> shift -> project" passes
-// (lbm_device.h).  One workgroup of 16 wavefronts owns a tile of 64 x 13
+// (lbm_device.h).  One workgroup of 15 wavefronts owns a tile of 64 x 12
 // output cells of an x-y plane and marches through z:
-//   - 15 row wavefronts: one 64-cell row each (a coalesced 256 B or 128 B
-//     row per plane), the 13 output rows plus one halo row above and below;
+//   - 14 row wavefronts: one 64-cell row each (a coalesced 256 B or 128 B
+//     row per plane), the 12 output rows plus one halo row above and below;
 //   - 1 column wavefront: the halo cells at x0 - 1 and x0 + 64 of those 15
 //     rows, so no lane of the row wavefronts is spent on halo cells.
 // Per plane every cell is loaded once and collided (App. A); then
@@ -29,7 +29,7 @@
 namespace lbm {
 
 #ifndef LBM_TILE_ROWS
-#define LBM_TILE_ROWS 13
+#define LBM_TILE_ROWS 12
 #endif
 #ifndef LBM_PREFETCH
 #define LBM_PREFETCH 1
@@ -279,7 +279,7 @@ void fluid_tiling(const Geometry& g, dim3* grid, dim3* block, int* ntx, int* nty
   *ntx = (g.nx + RW - 1) / RW;
   *nty = (g.ny + TYR - 1) / TYR;
   const uint64_t W = uint64_t(*ntx) * uint64_t(*nty) * uint64_t(g.nz);
-  // one workgroup per CU (it takes 1024 threads and ~122 KB of LDS); at least
+  // one workgroup per CU (960 threads and ~114 KB of LDS at 12 rows); at least
   // ~8 planes of work per workgroup
   uint64_t n = uint64_t(device_cus());
   const uint64_t cap = (W + 7) / 8;
