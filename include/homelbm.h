@@ -80,6 +80,8 @@ typedef struct lbm_options {
   int check_health;   /* 1 (default): lbm_step scans the state once at its end and
                          returns LBM_ERR_UNSTABLE if any stored value is non-finite
                          (FP32) or any code sits at 0 or 65535 (Q16) */
+  int tile_rows;      /* fluid-pass tile height: 0 (default) picks one from the grid
+                         shape; 8, 10, 12 or 13 force it.  Results do not depend on it. */
 } lbm_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -203,6 +205,16 @@ int lbm_synchronize(lbm_ctx* ctx);
  */
 int lbm_profile_steps(lbm_ctx* ctx, int n, double* fluid_ms, double* boundary_ms, int* fluid_launches,
                       int* boundary_launches);
+
+/*
+ * Host-only: the fluid pass's work split for a grid, without touching the
+ * device.  tile_rows as in lbm_options; cus = compute units of the device.
+ * out = {tile rows, tiles along x (64 cells each), tiles along y, z segments
+ * per tile, workgroups launched}.  Work item q (0 <= q < tiles * segments)
+ * is tile q % tiles in z segment q / tiles; workgroup w takes items w, w +
+ * workgroups, ...  Errors: LBM_ERR_INVALID_ARG.
+ */
+int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[5]);
 
 /*
  * Device-side dither generator, for known-answer tests: for each of the n

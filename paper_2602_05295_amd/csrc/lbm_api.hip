@@ -2,7 +2,9 @@
 // boundary list, step loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <iterator>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -141,7 +143,7 @@ int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
   const StepParams p = step_params(c, c->buf[c->cur], c->buf[1 - c->cur]);
   hipError_t e = hipSuccess;
   if (ev) e = hipEventRecord(ev[0], c->stream);
-  if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->stream);
+  if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->opt.tile_rows, c->stream);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "fluid pass");
   const int64_t n = c->n_fluid_b + c->n_solid_b;
@@ -252,8 +254,8 @@ int lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_OK;
   (void)hipStreamSynchronize(c->stream);
   for (int b = 0; b < 2; ++b)
-    if (c->buf[b]) hipFree(c->buf[b]);
-  if (c->d_mask) hipFree(c->d_mask);
+    if (c->buf[b]) (void)hipFree(c->buf[b]);
+  if (c->d_mask) (void)hipFree(c->d_mask);
   free_list(c);
   if (c->d_counters) (void)hipFree(c->d_counters);
   if (c->d_bad) (void)hipFree(c->d_bad);
@@ -271,6 +273,9 @@ int lbm_set_stream(lbm_ctx* c, void* s) {
 int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
   if (!c || !o) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
   if (o->dither_mode < 0 || o->dither_mode > 2) return fail(c, LBM_ERR_INVALID_ARG, "unknown dither mode");
+  if (o->tile_rows != 0 && std::find(std::begin(kFluidTileRows), std::end(kFluidTileRows), o->tile_rows) ==
+                               std::end(kFluidTileRows))
+    return fail(c, LBM_ERR_INVALID_ARG, "tile_rows must be 0, 8, 10, 12 or 13");
   int r = check_faces(c, *o);
   if (r != LBM_OK) return r;
   if (o->inflow && c->d_mask) {
@@ -323,7 +328,7 @@ int lbm_set_moments(lbm_ctx* c, const float* m, int on_device) {
   planes_of(c, c->buf[c->cur], pl);
   hipError_t e = launch_set_moments(c->fmt, static_cast<const float*>(dm), pl, c->d_mask, c->N, c->stream);
   if (e == hipSuccess && owned) e = hipStreamSynchronize(c->stream);
-  if (owned) hipFree(dm);
+  if (owned) (void)hipFree(dm);
   if (e != hipSuccess) return hip_fail(c, e, "set_moments");
   return LBM_OK;
 }
@@ -336,7 +341,7 @@ int lbm_set_equilibrium(lbm_ctx* c, const float* rho, const float* u, int on_dev
   if (r != LBM_OK) return r;
   r = stage_in(c, u, size_t(c->N) * 12, on_device, &du, &o2);
   if (r != LBM_OK) {
-    if (o1) hipFree(dr);
+    if (o1) (void)hipFree(dr);
     return r;
   }
   void* pl[10];
@@ -344,8 +349,8 @@ int lbm_set_equilibrium(lbm_ctx* c, const float* rho, const float* u, int on_dev
   hipError_t e = launch_set_equilibrium(c->fmt, static_cast<const float*>(dr), static_cast<const float*>(du), pl,
                                         c->d_mask, c->N, c->stream);
   if (e == hipSuccess && (o1 || o2)) e = hipStreamSynchronize(c->stream);
-  if (o1) hipFree(dr);
-  if (o2) hipFree(du);
+  if (o1) (void)hipFree(dr);
+  if (o2) (void)hipFree(du);
   if (e != hipSuccess) return hip_fail(c, e, "set_equilibrium");
   return LBM_OK;
 }
@@ -383,7 +388,7 @@ int lbm_get_moments(lbm_ctx* c, float* m, int on_device) {
   e = launch_get_moments(c->fmt, cpl, dm, c->d_mask, c->N, c->stream);
   if (e == hipSuccess && !on_device) e = hipMemcpyAsync(m, dm, size_t(c->N) * 40, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
-  if (!on_device) hipFree(dm);
+  if (!on_device) (void)hipFree(dm);
   if (e != hipSuccess) return hip_fail(c, e, "get_moments");
   return LBM_OK;
 }
@@ -474,7 +479,7 @@ int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, 
       tb += ms;
     }
   }
-  for (auto& x : ev) hipEventDestroy(x);
+  for (auto& x : ev) (void)hipEventDestroy(x);
   if (r != LBM_OK) return r;
   if (e != hipSuccess) return hip_fail(c, e, "profiling events");
   if (fluid_ms) *fluid_ms = tf;
@@ -526,6 +531,22 @@ int lbm_equilibrium_vjp(lbm_ctx* c, const float* rho, const float* u, const floa
   return LBM_OK;
 }
 
+int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[5]) {
+  if (!dims || !out || cus < 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "bad argument");
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "every dimension must be >= 1");
+  if (tile_rows != 0 &&
+      std::find(std::begin(kFluidTileRows), std::end(kFluidTileRows), tile_rows) == std::end(kFluidTileRows))
+    return fail(nullptr, LBM_ERR_INVALID_ARG, "tile_rows must be 0, 8, 10, 12 or 13");
+  const FluidPlan p = fluid_plan(Geometry{dims[0], dims[1], dims[2], 0}, tile_rows, cus);
+  out[0] = p.rows;
+  out[1] = p.ntx;
+  out[2] = p.nty;
+  out[3] = p.nseg;
+  out[4] = p.nwg;
+  return LBM_OK;
+}
+
 int lbm_debug_dither(int n, const uint32_t* idx, uint32_t t, uint32_t seed, int mode, uint32_t* h_out) {
   if (n < 0 || (n > 0 && (!idx || !h_out))) return fail(nullptr, LBM_ERR_INVALID_ARG, "bad argument");
   if (n == 0) return LBM_OK;
@@ -535,8 +556,8 @@ int lbm_debug_dither(int n, const uint32_t* idx, uint32_t t, uint32_t seed, int 
   if (e == hipSuccess) e = hipMemcpy(d_idx, idx, size_t(n) * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_debug_dither(n, d_idx, dither_key(t, seed, mode), d_out, nullptr);
   if (e == hipSuccess) e = hipMemcpy(h_out, d_out, size_t(n) * 8, hipMemcpyDeviceToHost);
-  if (d_idx) hipFree(d_idx);
-  if (d_out) hipFree(d_out);
+  if (d_idx) (void)hipFree(d_idx);
+  if (d_out) (void)hipFree(d_out);
   if (e != hipSuccess) return hip_fail(nullptr, e, "debug_dither");
   return LBM_OK;
 }

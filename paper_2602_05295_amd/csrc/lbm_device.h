@@ -431,6 +431,13 @@ __device__ inline void encode_cell(float dr, const float j[3], const float P[6],
 }
 
 // ------------------------------------------------------------ int helpers ---
+// Workgroups are dispatched to the 8 XCDs round-robin (block b to XCD b % 8).
+// This renumbers n blocks so that the blocks of one XCD are consecutive.
+__device__ inline int xcd_logical_block(int b, int n) {
+  const int x = b & 7, k = b >> 3;
+  return x * (n >> 3) + min(x, n & 7) + k;
+}
+
 __device__ inline int wrapi(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;

@@ -18,29 +18,28 @@
 // Only the ten new moments are written.  The next plane's state is loaded
 // while the current one is computed.
 //
-// The grid is persistent: every workgroup takes an equal contiguous range of
-// the (tile, z) work list, tile-major, so it marches one or two z segments;
-// workgroups on the same XCD (round-robin dispatch) get neighbouring ranges so
-// that halo re-reads stay in that XCD's L2.  Every axis is treated as periodic
-// here; faces and walls are overwritten afterwards by the boundary pass.
+// Work items are (tile, z segment) pairs.  Every tile's z range is cut into
+// the same S equal segments, so all items of a wave start on the same plane
+// and advance in step: a tile's halo rows and columns are then read while the
+// neighbouring tile that owns them holds the same planes in L2.  Items are
+// numbered segment-major, tile-minor (x fastest) and the workgroups of one
+// XCD (round-robin dispatch) take consecutive numbers, so each XCD works on a
+// compact band of tiles.  The host picks the tile height and S from the
+// domain shape.  Every axis is treated as periodic here; faces and walls are
+// overwritten afterwards by the boundary pass.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
+#include <algorithm>
+
 namespace lbm {
 
-#ifndef LBM_TILE_ROWS
-#define LBM_TILE_ROWS 12
-#endif
-#ifndef LBM_PREFETCH
-#define LBM_PREFETCH 1
-#endif
-constexpr int RW = 64;               // cells per row wavefront
-constexpr int TYR = LBM_TILE_ROWS;   // output rows per tile
-constexpr int NRW = TYR + 2;         // row wavefronts (with the two halo rows)
-constexpr int NTH = (NRW + 1) * RW;  // plus the halo-column wavefront
+constexpr int RW = 64;  // cells per row wavefront
 
+// LDS of a tile with TYR output rows (TYR + 2 row wavefronts).
+template <int TYR>
 struct FluidLds {
-  float ly[16][NRW][RW];      // y movers (+, -) of 8 groups, row wavefronts
+  float ly[16][TYR + 2][RW];  // y movers (+, -) of 8 groups, row wavefronts
   float lyc[16][2][16];       // y movers of the two halo columns
   float lx[18][TYR][RW + 2];  // x movers (+, -) of 9 groups, with halo columns at 0 and RW + 1
 };
@@ -95,9 +94,10 @@ __device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, 
 
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-template <int FMT>
-__global__ void __launch_bounds__(NTH) fluid_kernel(StepParams a, int ntx, int nty, int nwg) {
-  __shared__ FluidLds L;
+template <int FMT, int TYR>
+__global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg) {
+  constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
+  __shared__ FluidLds<TYR> L;
 
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
@@ -117,19 +117,14 @@ __global__ void __launch_bounds__(NTH) fluid_kernel(StepParams a, int ntx, int n
   const bool inner = r >= 1 && r <= TYR;  // a row whose y and x passes are needed
   const bool compute = !colw && inner;    // a row wavefront with outputs
 
-  // this workgroup's range of the (tile, z) work list; XCD-grouped
-  const int b = int(blockIdx.x);
-  const int lb = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
-  const uint64_t W = uint64_t(ntx) * uint64_t(nty) * uint64_t(nz);
-  uint64_t w = W * uint64_t(lb) / uint64_t(nwg);
-  const uint64_t wend = W * uint64_t(lb + 1) / uint64_t(nwg);
+  const int ntiles = ntx * nty;
+  const int items = ntiles * nseg;
   const uint32_t plane = uint32_t(nx) * uint32_t(ny);
 
-  while (w < wend) {
-    const int t = int(w / uint64_t(nz));
-    const int za = int(w % uint64_t(nz));
-    const int zb = int(min(uint64_t(nz), uint64_t(za) + (wend - w)));
-    w += uint64_t(zb - za);
+  for (int q = xcd_logical_block(int(blockIdx.x), nwg); q < items; q += nwg) {
+    const int t = q % ntiles, sg = q / ntiles;
+    const int za = int(int64_t(nz) * sg / nseg);
+    const int zb = int(int64_t(nz) * (sg + 1) / nseg);
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
     const int xw = wrapi(gx, nx), yw = wrapi(gy, ny);
@@ -140,21 +135,11 @@ __global__ void __launch_bounds__(NTH) fluid_kernel(StepParams a, int ntx, int n
 #pragma unroll
     for (int g = 0; g < 6; ++g) wp2[g] = wp1[g] = w0[g] = 0.0f;
 
-#if LBM_PREFETCH >= 2
-    // two planes in flight ahead of the one being computed
-    Raw<FMT> nxt1 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za - 1, nz))) * 4u);
-    Raw<FMT> nxt2 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za, nz))) * 4u);
-    for (int p = za - 1; p <= zb; ++p) {
-      const Raw<FMT> cur = nxt1;
-      nxt1 = nxt2;
-      if (p + 2 <= zb) nxt2 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 2, nz))) * 4u);
-#else
     // the next plane in flight while the current one is computed
     Raw<FMT> nxt1 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za - 1, nz))) * 4u);
     for (int p = za - 1; p <= zb; ++p) {
       const Raw<FMT> cur = nxt1;
       if (p + 1 <= zb) nxt1 = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
-#endif
 
       const CellIn c = decode<FMT>(cur);
       float Nn[6];
@@ -273,32 +258,72 @@ int device_cus() {
   }
   return cached[dev];
 }
+
+template <int FMT>
+hipError_t launch_rows(int rows, dim3 grid, const StepParams& p, int ntx, int nty, int nseg, int nwg, hipStream_t s) {
+  switch (rows) {
+    case 8:
+      hipLaunchKernelGGL((fluid_kernel<FMT, 8>), grid, dim3(11 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      break;
+    case 10:
+      hipLaunchKernelGGL((fluid_kernel<FMT, 10>), grid, dim3(13 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      break;
+    case 12:
+      hipLaunchKernelGGL((fluid_kernel<FMT, 12>), grid, dim3(15 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      break;
+    default:
+      hipLaunchKernelGGL((fluid_kernel<FMT, 13>), grid, dim3(16 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      break;
+  }
+  return hipGetLastError();
+}
 }  // namespace
 
-void fluid_tiling(const Geometry& g, dim3* grid, dim3* block, int* ntx, int* nty, int* nwg) {
-  *ntx = (g.nx + RW - 1) / RW;
-  *nty = (g.ny + TYR - 1) / TYR;
-  const uint64_t W = uint64_t(*ntx) * uint64_t(*nty) * uint64_t(g.nz);
-  // one workgroup per CU (960 threads and ~114 KB of LDS at 12 rows); at least
-  // ~8 planes of work per workgroup
-  uint64_t n = uint64_t(device_cus());
-  const uint64_t cap = (W + 7) / 8;
-  if (n > cap) n = cap;
-  if (n < 1) n = 1;
-  *nwg = int(n);
-  *grid = dim3(uint32_t(n));
-  *block = dim3(NTH);
+const int kFluidTileRows[4] = {8, 10, 12, 13};
+
+FluidPlan fluid_plan(const Geometry& g, int rows, int cus) {
+  FluidPlan best{};
+  double best_cost = 0.0;
+  for (int r : kFluidTileRows) {
+    if (rows != 0 && r != rows) continue;
+    FluidPlan c{};
+    c.rows = r;
+    c.ntx = (g.nx + RW - 1) / RW;
+    c.nty = (g.ny + r - 1) / r;
+    const int64_t T = int64_t(c.ntx) * c.nty;
+    // split z so that one wave of items fills the CUs when there are fewer
+    // tiles than CUs; then pick the split with the shortest critical path
+    double cost_best = 0.0;
+    int seg_best = 1;
+    const int smax = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(g.nz) / 4, 64)));
+    for (int sgs = 1; sgs <= smax; ++sgs) {
+      const int64_t items = T * sgs;
+      const int64_t waves = (items + cus - 1) / cus;
+      const int64_t planes = (g.nz + sgs - 1) / sgs + 2;  // two extra planes start each segment
+      // time of one plane of one tile ~ the wavefronts of the workgroup
+      const double cost = double(waves) * double(planes) * double(r + 3);
+      if (sgs == 1 || cost < cost_best) {
+        cost_best = cost;
+        seg_best = sgs;
+      }
+    }
+    c.nseg = seg_best;
+    const int64_t items = T * seg_best;
+    c.nwg = int(std::min<int64_t>(items, cus));
+    if (best.rows == 0 || cost_best < best_cost) {
+      best = c;
+      best_cost = cost_best;
+    }
+  }
+  return best;
 }
 
-hipError_t launch_fluid(int fmt, const StepParams& p, hipStream_t s) {
-  dim3 grid, block;
-  int ntx, nty, nwg;
-  fluid_tiling(p.g, &grid, &block, &ntx, &nty, &nwg);
-  if (fmt == FMT_F32)
-    hipLaunchKernelGGL(fluid_kernel<FMT_F32>, grid, block, 0, s, p, ntx, nty, nwg);
-  else
-    hipLaunchKernelGGL(fluid_kernel<FMT_Q16>, grid, block, 0, s, p, ntx, nty, nwg);
-  return hipGetLastError();
+hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {
+  const FluidPlan c = fluid_plan(p.g, rows, device_cus());
+  if (c.rows == 0) return hipErrorInvalidValue;
+  const dim3 grid(uint32_t(c.nwg));
+  if (fmt == FMT_F32) return launch_rows<FMT_F32>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  return launch_rows<FMT_Q16>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
 }
 
 }  // namespace lbm

@@ -44,8 +44,17 @@ hipError_t launch_adjoint_flags(const uint8_t* mask, int64_t N, const uint32_t* 
 hipError_t launch_equilibrium_vjp(const float* rho, const float* u, const float* lam, const uint8_t* mask, int64_t N,
                                   float* grho, float* gu, hipStream_t s);
 
-// Fused fluid pass over every cell (all axes treated periodic).
-hipError_t launch_fluid(int fmt, const StepParams& p, hipStream_t s);
+// Fused fluid pass over every cell (all axes treated periodic).  rows: tile
+// height (one of kFluidTileRows) or 0 to let fluid_plan choose.
+struct FluidPlan {
+  int rows;  // output rows per tile
+  int ntx, nty;
+  int nseg;  // z segments per tile
+  int nwg;   // workgroups launched
+};
+extern const int kFluidTileRows[4];
+FluidPlan fluid_plan(const Geometry& g, int rows, int cus);
+hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s);
 
 // Boundary pass over the compacted list.
 hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits, int count,

@@ -36,6 +36,7 @@ class Options(ctypes.Structure):
         ("inflow", ctypes.c_int),
         ("u_in", ctypes.c_float * 3),
         ("check_health", ctypes.c_int),
+        ("tile_rows", ctypes.c_int),
     ]
 
 
@@ -87,6 +88,7 @@ def lib():
     L.lbm_debug_dither.argtypes = [i, vp, ctypes.c_uint32, ctypes.c_uint32, i, vp]
     L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
     L.lbm_equilibrium_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.lbm_fluid_plan.argtypes = [P(i), i, i, P(i)]
     _lib = L
     return L
 
@@ -118,6 +120,17 @@ def debug_dither(idx, t, seed, mode):
     if st != OK:
         raise LBMError(st, lib().lbm_last_error(None).decode())
     return out
+
+
+def fluid_plan(dims, tile_rows=0, cus=256):
+    """The fluid pass's work split (host only): dict of tile rows, tiles along
+    x and y, z segments per tile and workgroups launched."""
+    d = (ctypes.c_int * 3)(*[int(v) for v in dims])
+    out = (ctypes.c_int * 5)()
+    st = lib().lbm_fluid_plan(d, int(tile_rows), int(cus), out)
+    if st != OK:
+        raise LBMError(st, lib().lbm_last_error(None).decode())
+    return dict(zip(("rows", "ntx", "nty", "nseg", "nwg"), list(out)))
 
 
 class HomeLBM:
@@ -179,7 +192,7 @@ class HomeLBM:
         self._check(lib().lbm_get_options(self._h, ctypes.byref(o)))
         return o
 
-    def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None):
+    def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None, tile_rows=None):
         o = self.options()
         if dither_mode is not None:
             o.dither_mode = int(dither_mode)
@@ -191,6 +204,8 @@ class HomeLBM:
             o.u_in = (ctypes.c_float * 3)(*[float(v) for v in u_in])
         if check_health is not None:
             o.check_health = int(bool(check_health))
+        if tile_rows is not None:
+            o.tile_rows = int(tile_rows)
         self._check(lib().lbm_set_options(self._h, ctypes.byref(o)))
 
     def set_stream(self, stream):

@@ -2,6 +2,8 @@
 exports every function include/homelbm.h declares; the header's option
 struct matches the binding's."""
 import ctypes
+
+import pytest
 import os
 import re
 
@@ -23,7 +25,7 @@ def test_options_struct_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"(\w+)\s+(\w+)(\[\d+\])?;", body)
     assert [f[1] for f in fields] == [f[0] for f in homelbm.Options._fields_]
-    assert ctypes.sizeof(homelbm.Options) == 4 * 7
+    assert ctypes.sizeof(homelbm.Options) == 4 * 8
 
 
 def test_default_options_without_gpu():
@@ -53,3 +55,25 @@ def test_no_oracle_in_product_path():
                     src = fh.read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "homelbm_oracle" not in src, f
+
+
+def test_fluid_plan_host_logic():
+    """The fluid pass's work split: every item maps to a tile and a z segment,
+    one wave of items fills the CUs when tiles are fewer than CUs, and the
+    forced heights are honoured."""
+    plan = homelbm.fluid_plan
+    p = plan((256, 256, 256))
+    tiles = p["ntx"] * p["nty"]
+    assert p["ntx"] == 4 and p["nty"] == -(-256 // p["rows"])
+    assert tiles * p["nseg"] <= 256 and p["nwg"] == tiles * p["nseg"]
+    assert tiles * (p["nseg"] + 1) > 256  # no further split fits in one wave
+    q = plan((1000, 400, 400))
+    assert q["ntx"] == 16 and q["nwg"] == 256
+    for rows in (8, 10, 12, 13):
+        r = plan((130, 53, 40), tile_rows=rows)
+        assert r["rows"] == rows and r["ntx"] == 3 and r["nty"] == -(-53 // rows)
+        assert 1 <= r["nwg"] <= 256 and r["nseg"] >= 1
+    t = plan((1, 1, 1))
+    assert t["nwg"] == 1 and t["nseg"] == 1
+    with pytest.raises(homelbm.LBMError):
+        plan((8, 8, 8), tile_rows=7)

@@ -53,6 +53,44 @@ def test_fp32_one_step_random(H, orc, dims):
     assert max(err.values()) <= TOL32, err
 
 
+@pytest.mark.parametrize("rows", [8, 10, 12, 13])
+def test_fp32_tile_heights_agree_with_oracle_and_each_other(H, orc, rows):
+    """Every tile height, with ragged tiles in x and y and several z segments,
+    gives the oracle's step and the same bits as the automatic choice."""
+    dims = (130, 53, 40)
+    _note("fp32 tile rows", rows, dims)
+    m = W.random_moments(*dims, seed=21).astype(np.float32)
+    outs = {}
+    for tr in (0, rows):
+        with H.HomeLBM(dims, 0.57) as s:
+            s.set_options(tile_rows=tr)
+            s.set_moments(m)
+            s.step(2)
+            outs[tr] = s.get_raw()
+    assert np.array_equal(outs[0], outs[rows])
+    P = _orc_params(orc, dims, 0.57)
+    ref = orc.step(P, orc.step(P, m.astype(np.float64)))
+    got = outs[rows].astype(np.float64)
+    got[0] += 1.0
+    err = group_rel_err(got, ref)
+    assert max(err.values()) <= TOL32, err
+
+
+@pytest.mark.parametrize("rows", [8, 13])
+def test_q16_tile_heights_same_codes(H, rows):
+    dims = (97, 40, 33)
+    _note("q16 tile rows", rows, dims)
+    m = W.random_moments(*dims, seed=22, dj=0.02, dp=0.003).astype(np.float32)
+    outs = {}
+    for tr in (0, rows):
+        with H.HomeLBM(dims, 0.58, fmt="q16") as s:
+            s.set_options(tile_rows=tr, dither_mode=1, seed=3)
+            s.set_moments(m)
+            s.step(3)
+            outs[tr] = s.get_raw()
+    assert np.array_equal(outs[0], outs[rows])
+
+
 def test_fp32_taylor_green_100_steps(H, orc):
     _note("fp32 TGV 32^3 100 steps")
     rho, u = W.taylor_green_2d(32, 32, 32, 0.05)
