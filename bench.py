@@ -182,6 +182,45 @@ def channel(steps=20):
             "unhealthy_values": int(bad)}
 
 
+def batched(steps=200):
+    """128 periodic domains of seeded sizes 24^3..96^3 with sphere obstacles
+    (0-10% solid) and tau in [0.52, 0.8], 16-bit moments: the autotuned work
+    split, then `steps` steps replayed from one captured HIP graph."""
+    import torch
+    from paper_2602_05295_amd import workloads as W
+    from paper_2602_05295_amd.homelbm import HomeLBMBatch
+    doms = W.batched_domains(128, seed=0)
+    fields = [W.batched_domain_fields(d) for d in doms]
+    dims = [d["dims"] for d in doms]
+    stream = torch.cuda.current_stream()
+    with HomeLBMBatch(dims, [d["tau"] for d in doms], [f[0] for f in fields], fmt="q16",
+                      stream=stream.cuda_stream) as b:
+        b.set_options(check_health=False)
+        for k, (mask, u) in enumerate(fields):
+            b.set_equilibrium(k, np.ones(mask.shape, np.float32), u.astype(np.float32))
+        tuning = b.tune()
+        b.step(steps)  # captures the graph and warms up
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        b.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        prof = b.profile_steps(20)
+        nf, ns = b.boundary_counts()
+        bad = b.check()
+        cells = b.cells()
+    fl = prof["fluid_ms"] / prof["steps"]
+    return {"config": "128 domains 24..96 per axis, 0-10% spheres, tau 0.52-0.8, 16-bit, one graph of "
+                      f"{steps} steps", "cells": int(cells), "boundary_fluid_cells": nf, "boundary_solid_cells": ns,
+            "mlups": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "fluid_kernel_ms": round(fl, 4), "boundary_kernel_ms": round(prof["boundary_ms"] / prof["steps"], 4),
+            "fluid_GBs": round(cells * 40 / (fl * 1e-3) / 1e9, 1),
+            "tuning": {k: tuning[k] for k in ("block", "wg_per_cu", "workgroups", "segments", "balance")},
+            "unhealthy_values": int(bad)}
+
+
 def cpu_baseline(u, steps=8):
     """The FP64 oracle on the host, untuned: `steps` steps of the same 256^3
     field on all host threads (about 10-20 s)."""
@@ -244,6 +283,9 @@ def main():
         print("[bench] 1000x400x400 channel", file=sys.stderr, flush=True)
         extras["channel"] = channel()
         print(f"[bench] {extras['channel']}", file=sys.stderr, flush=True)
+        print("[bench] 128-domain batch", file=sys.stderr, flush=True)
+        extras["batched"] = batched()
+        print(f"[bench] {extras['batched']}", file=sys.stderr, flush=True)
     print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u)
     if "q16" not in res or "fp32" not in res:
@@ -281,6 +323,7 @@ def main():
         "adjoint_forward_ratio": extras.get("adjoint", {}).get("ratio"),
         "adjoint": extras.get("adjoint"),
         "channel_1000x400x400": extras.get("channel"),
+        "batched_128_domains": extras.get("batched"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

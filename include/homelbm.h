@@ -223,6 +223,102 @@ int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[5]);
  */
 int lbm_debug_dither(int n, const uint32_t* idx, uint32_t t, uint32_t seed, int mode, uint32_t* h_out);
 
+/* ======================================================================
+ * Batched step: many independent small domains advanced together.
+ *
+ * The same step as above (fluid pass, then the boundary pass over listed
+ * cells) applied to `count` periodic domains of their own sizes, relaxation
+ * times and solid masks.  One fluid launch covers every domain (a persistent
+ * grid walking a host-built list of strips and z runs) and one boundary
+ * launch covers every listed cell; lbm_batch_step captures a sequence of
+ * steps in a HIP graph once and replays it.  A domain's result is the one the
+ * single-domain API gives it with the same options and step count, up to the
+ * order of float rounding.
+ * ====================================================================== */
+typedef struct lbm_batch lbm_batch;
+
+/* Work split of the batched fluid pass (see lbm_batch_tune). */
+typedef struct lbm_batch_tuning {
+  int block;         /* threads per fluid workgroup: 256, 512 or 1024 */
+  int wg_per_cu;     /* persistent workgroups per compute unit */
+  int workgroups;    /* workgroups launched */
+  int segments;      /* (strip, z run) work units in the split */
+  double balance;    /* mean / largest workgroup load of the split (1 = even) */
+  double fluid_ms;   /* measured fluid-pass time of this split (0 if not timed) */
+  int from_cache;    /* 1: read from the autotune cache instead of measured */
+} lbm_batch_tuning;
+
+/*
+ * Creates a batch of `count` (1..65535) domains.  dims: 3*count ints (nx, ny,
+ * nz of each domain, each 1..65535; nx <= 341 unless nx*ny <= 1024); taus:
+ * count relaxation times > 1/2; masks: NULL, or count host pointers, each NULL
+ * (no solids) or nx*ny*nz bytes of 0/1 (copied).  Total cells <= 2^30.
+ * moment_format as in lbm_create.  Every domain starts at rest; every axis is
+ * periodic.  Errors: LBM_ERR_INVALID_ARG, LBM_ERR_OUT_OF_MEMORY, LBM_ERR_DEVICE.
+ */
+int lbm_batch_create(int count, const int* dims, const double* taus, const uint8_t* const* masks,
+                     int moment_format, lbm_batch** out);
+int lbm_batch_destroy(lbm_batch* b);
+const char* lbm_batch_last_error(const lbm_batch* b);
+int lbm_batch_set_stream(lbm_batch* b, void* hip_stream);
+/* dither_mode, seed and check_health as in lbm_options; inflow and tile_rows
+ * must be 0 (LBM_ERR_UNSUPPORTED / LBM_ERR_INVALID_ARG otherwise). */
+int lbm_batch_set_options(lbm_batch* b, const lbm_options* opt);
+int lbm_batch_get_options(const lbm_batch* b, lbm_options* opt);
+/* dims of domain d, its first cell in the batch's planes and its cell count. */
+int lbm_batch_info(const lbm_batch* b, int d, int dims[3], int64_t* offset, int64_t* cells);
+int lbm_batch_total_cells(const lbm_batch* b, int64_t* cells);
+/* Per-domain state access, with the layouts and conventions of the
+ * single-domain calls of the same names (d = domain index). */
+int lbm_batch_set_moments(lbm_batch* b, int d, const float* m, int on_device);
+int lbm_batch_set_equilibrium(lbm_batch* b, int d, const float* rho, const float* u, int on_device);
+int lbm_batch_get_moments(lbm_batch* b, int d, float* m, int on_device);
+size_t lbm_batch_raw_bytes(const lbm_batch* b, int d);
+int lbm_batch_get_raw(lbm_batch* b, int d, void* out, size_t bytes, int on_device);
+int lbm_batch_set_raw(lbm_batch* b, int d, const void* in, size_t bytes, int on_device);
+/*
+ * Advances every domain n steps, asynchronously on the batch stream: up to
+ * 256 steps are captured once per (length, buffer parity) in a HIP graph and
+ * replayed (the dither key of each step is read from a device-side step
+ * counter, so a graph is valid at any step).  With check_health set, the
+ * state is scanned once at the end (synchronising).
+ */
+int lbm_batch_step(lbm_batch* b, int n);
+/* The same n steps launched one kernel at a time (no graph). */
+int lbm_batch_step_eager(lbm_batch* b, int n);
+/* n eager steps with HIP events around each launch; sums of the fluid and
+ * boundary launch times in ms.  Synchronous. */
+int lbm_batch_profile_steps(lbm_batch* b, int n, double* fluid_ms, double* boundary_ms);
+int lbm_batch_get_step_count(const lbm_batch* b, uint64_t* t);
+int lbm_batch_set_step_count(lbm_batch* b, uint64_t t);
+int lbm_batch_boundary_counts(const lbm_batch* b, int64_t* fluid_cells, int64_t* solid_cells);
+int lbm_batch_memory_bytes(const lbm_batch* b, size_t* state_bytes, size_t* total_bytes);
+int lbm_batch_check(lbm_batch* b, uint64_t* bad);
+int lbm_batch_synchronize(lbm_batch* b);
+/*
+ * Autotuner: times the fluid pass under every workgroup shape that fits
+ * every domain (256, 512 or 1024 threads; 1, 2 or 4 per CU as occupancy
+ * allows) on the current state (writing only the idle buffer) and keeps the
+ * fastest.  cache_path (or, when NULL, the LBM_AUTOTUNE_CACHE environment
+ * variable; neither: no cache) names a JSON file keyed by device, format and
+ * domain shapes: a hit applies the stored shape without timing, a miss adds
+ * the result.  *result (may be NULL) receives the chosen split.
+ */
+int lbm_batch_tune(lbm_batch* b, const char* cache_path, lbm_batch_tuning* result);
+int lbm_batch_get_tuning(const lbm_batch* b, lbm_batch_tuning* t);
+int lbm_batch_set_tuning(lbm_batch* b, int block, int wg_per_cu);
+/*
+ * Host-only: the work split for domains `dims` (3*count ints) with `block`
+ * threads per workgroup and nwg workgroups, without touching the device.
+ * On entry *n_segments is the capacity of `segments` (4 uint16 per segment:
+ * domain, strip, first plane, end plane; may be NULL to query the count);
+ * wg_first (nwg + 1, may be NULL) receives each workgroup's first segment;
+ * strips (3*count, may be NULL) receives rows loaded, output rows and the
+ * whole-plane flag of each domain's strips; balance as in lbm_batch_tuning.
+ */
+int lbm_batch_plan(int count, const int* dims, int block, int nwg, int* n_segments, uint16_t* segments,
+                   uint32_t* wg_first, int* strips, double* balance);
+
 #ifdef __cplusplus
 }
 #endif

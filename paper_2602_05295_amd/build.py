@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build", "homelbm")
 LIB = os.path.join(PKG, "libhomelbm.so")
 
-SOURCES = ["lbm_api.hip", "lbm_fluid.hip", "lbm_boundary.hip", "lbm_aux.hip", "lbm_adjoint.hip"]
+SOURCES = ["lbm_api.hip", "lbm_fluid.hip", "lbm_boundary.hip", "lbm_aux.hip", "lbm_adjoint.hip",
+           "lbm_batch.hip", "lbm_batch_api.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = "gfx950"

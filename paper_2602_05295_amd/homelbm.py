@@ -40,6 +40,21 @@ class Options(ctypes.Structure):
     ]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int),
+        ("wg_per_cu", ctypes.c_int),
+        ("workgroups", ctypes.c_int),
+        ("segments", ctypes.c_int),
+        ("balance", ctypes.c_double),
+        ("fluid_ms", ctypes.c_double),
+        ("from_cache", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -89,6 +104,37 @@ def lib():
     L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
     L.lbm_equilibrium_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_fluid_plan.argtypes = [P(i), i, i, P(i)]
+    # batched API
+    L.lbm_batch_create.argtypes = [i, P(i), P(ctypes.c_double), P(vp), i, P(vp)]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_last_error.argtypes = [vp]
+    L.lbm_batch_last_error.restype = ctypes.c_char_p
+    L.lbm_batch_set_stream.argtypes = [vp, vp]
+    L.lbm_batch_set_options.argtypes = [vp, P(Options)]
+    L.lbm_batch_get_options.argtypes = [vp, P(Options)]
+    L.lbm_batch_info.argtypes = [vp, i, P(i), P(ctypes.c_int64), P(ctypes.c_int64)]
+    L.lbm_batch_total_cells.argtypes = [vp, P(ctypes.c_int64)]
+    L.lbm_batch_set_moments.argtypes = [vp, i, vp, i]
+    L.lbm_batch_set_equilibrium.argtypes = [vp, i, vp, vp, i]
+    L.lbm_batch_get_moments.argtypes = [vp, i, vp, i]
+    L.lbm_batch_raw_bytes.argtypes = [vp, i]
+    L.lbm_batch_raw_bytes.restype = sz
+    L.lbm_batch_get_raw.argtypes = [vp, i, vp, sz, i]
+    L.lbm_batch_set_raw.argtypes = [vp, i, vp, sz, i]
+    L.lbm_batch_step.argtypes = [vp, i]
+    L.lbm_batch_step_eager.argtypes = [vp, i]
+    L.lbm_batch_profile_steps.argtypes = [vp, i, P(ctypes.c_double), P(ctypes.c_double)]
+    L.lbm_batch_get_step_count.argtypes = [vp, P(ctypes.c_uint64)]
+    L.lbm_batch_set_step_count.argtypes = [vp, ctypes.c_uint64]
+    L.lbm_batch_boundary_counts.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    L.lbm_batch_memory_bytes.argtypes = [vp, P(sz), P(sz)]
+    L.lbm_batch_check.argtypes = [vp, P(ctypes.c_uint64)]
+    L.lbm_batch_synchronize.argtypes = [vp]
+    L.lbm_batch_tune.argtypes = [vp, ctypes.c_char_p, P(BatchTuning)]
+    L.lbm_batch_get_tuning.argtypes = [vp, P(BatchTuning)]
+    L.lbm_batch_set_tuning.argtypes = [vp, i, i]
+    L.lbm_batch_plan.argtypes = [i, P(i), i, i, P(i), P(ctypes.c_uint16), P(ctypes.c_uint32), P(i),
+                                 P(ctypes.c_double)]
     _lib = L
     return L
 
@@ -314,6 +360,219 @@ class HomeLBM:
                                             ctypes.byref(nb)))
         return {"fluid_ms": f.value, "boundary_ms": b.value, "fluid_launches": nf.value,
                 "boundary_launches": nb.value}
+
+
+def batch_plan(dims_list, block=1024, nwg=256):
+    """Host-only work split of the batched fluid pass: dict with the segments
+    ((domain, strip, first plane, end plane) rows), each workgroup's first
+    segment, each domain's (rows loaded, output rows, whole-plane flag) and
+    the balance (mean / largest workgroup load)."""
+    dims = np.ascontiguousarray(np.asarray(dims_list, dtype=np.int32).reshape(-1, 3))
+    count = dims.shape[0]
+    n = ctypes.c_int(0)
+    dp = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    L = lib()
+    st = L.lbm_batch_plan(count, dp, block, nwg, ctypes.byref(n), None, None, None, None)
+    if st != OK:
+        raise LBMError(st, L.lbm_batch_last_error(None).decode())
+    segs = np.zeros((max(n.value, 1), 4), np.uint16)
+    first = np.zeros(nwg + 1, np.uint32)
+    strips = np.zeros((count, 3), np.int32)
+    bal = ctypes.c_double()
+    st = L.lbm_batch_plan(count, dp, block, nwg, ctypes.byref(n), segs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                          first.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                          strips.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(bal))
+    if st != OK:
+        raise LBMError(st, L.lbm_batch_last_error(None).decode())
+    return {"segments": segs[:n.value], "wg_first": first, "strips": strips, "balance": bal.value}
+
+
+class HomeLBMBatch:
+    """Many independent periodic HOME-LBM domains advanced together."""
+
+    def __init__(self, dims_list, taus, masks=None, fmt="q16", stream=None, **options):
+        L = lib()
+        self.dims = [tuple(int(v) for v in d) for d in dims_list]
+        self.count = len(self.dims)
+        if len(taus) != self.count:
+            raise ValueError("one tau per domain")
+        self.fmt = {"fp32": FP32, "q16": Q16, FP32: FP32, Q16: Q16}[fmt]
+        self.taus = [float(t) for t in taus]
+        flat = (ctypes.c_int * (3 * self.count))(*[v for d in self.dims for v in d])
+        tau_arr = (ctypes.c_double * self.count)(*self.taus)
+        self._masks = []
+        mptr = None
+        if masks is not None:
+            if len(masks) != self.count:
+                raise ValueError("one mask (or None) per domain")
+            mptr = (ctypes.c_void_p * self.count)()
+            for k, m in enumerate(masks):
+                if m is None:
+                    self._masks.append(None)
+                    mptr[k] = None
+                    continue
+                a = np.ascontiguousarray(m, dtype=np.uint8)
+                if a.size != int(np.prod(self.dims[k])):
+                    raise ValueError(f"mask {k} must have nx*ny*nz entries")
+                self._masks.append(a)
+                mptr[k] = a.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        self._h = None
+        st = L.lbm_batch_create(self.count, flat, tau_arr, mptr, self.fmt, ctypes.byref(h))
+        if st != OK:
+            raise LBMError(st, L.lbm_batch_last_error(None).decode())
+        self._h = h
+        if stream is None:
+            stream = _torch_stream()
+        if stream is not None:
+            self._check(L.lbm_batch_set_stream(self._h, ctypes.c_void_p(stream)))
+        if options:
+            self.set_options(**options)
+
+    def _check(self, st):
+        if st != OK:
+            msg = lib().lbm_batch_last_error(self._h)
+            raise LBMError(st, msg.decode() if msg else "")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def options(self) -> Options:
+        o = Options()
+        self._check(lib().lbm_batch_get_options(self._h, ctypes.byref(o)))
+        return o
+
+    def set_options(self, dither_mode=None, seed=None, check_health=None):
+        o = self.options()
+        if dither_mode is not None:
+            o.dither_mode = int(dither_mode)
+        if seed is not None:
+            o.seed = int(seed) & 0xFFFFFFFF
+        if check_health is not None:
+            o.check_health = int(bool(check_health))
+        self._check(lib().lbm_batch_set_options(self._h, ctypes.byref(o)))
+
+    def _dom(self, d):
+        d = int(d)
+        if not 0 <= d < self.count:
+            raise LBMError(ERR_INVALID_ARG, f"domain index {d} out of range 0..{self.count - 1}")
+        return d
+
+    def cells(self, d=None):
+        if d is None:
+            n = ctypes.c_int64()
+            self._check(lib().lbm_batch_total_cells(self._h, ctypes.byref(n)))
+            return n.value
+        return int(np.prod(self.dims[self._dom(d)]))
+
+    def set_moments(self, d, m):
+        p, dev, keep = _ptr(m, np.float32, 10 * self.cells(d))
+        self._check(lib().lbm_batch_set_moments(self._h, int(d), p, dev))
+
+    def set_equilibrium(self, d, rho, u):
+        n = self.cells(d)
+        p1, d1, k1 = _ptr(rho, np.float32, n)
+        p2, d2, k2 = _ptr(u, np.float32, 3 * n)
+        if d1 != d2:
+            raise ValueError("rho and u must both be host arrays or both device tensors")
+        self._check(lib().lbm_batch_set_equilibrium(self._h, int(d), p1, p2, d1))
+
+    def get_moments(self, d, out=None):
+        shape = (10,) + self.dims[self._dom(d)][::-1]
+        if out is None:
+            out = np.empty(shape, dtype=np.float32)
+        p, dev, keep = _ptr(out, np.float32, int(np.prod(shape)))
+        self._check(lib().lbm_batch_get_moments(self._h, int(d), p, dev))
+        return out
+
+    def raw_bytes(self, d):
+        return lib().lbm_batch_raw_bytes(self._h, int(d))
+
+    def get_raw(self, d, out=None):
+        """Raw state of domain d: FP32 (10, nz, ny, nx) float32, Q16 (5, nz, ny, nx) uint32."""
+        shape = ((10,) if self.fmt == FP32 else (5,)) + self.dims[self._dom(d)][::-1]
+        dt = np.float32 if self.fmt == FP32 else np.uint32
+        if out is None:
+            out = np.empty(shape, dtype=dt)
+        p, dev, keep = _ptr(out, dt, int(np.prod(shape)))
+        self._check(lib().lbm_batch_get_raw(self._h, int(d), p, self.raw_bytes(d), dev))
+        return out
+
+    def set_raw(self, d, raw):
+        dt = np.float32 if self.fmt == FP32 else np.uint32
+        n = (10 if self.fmt == FP32 else 5) * self.cells(d)
+        p, dev, keep = _ptr(raw, dt, n)
+        self._check(lib().lbm_batch_set_raw(self._h, int(d), p, self.raw_bytes(d), dev))
+
+    def step(self, n=1):
+        """n steps replayed from captured HIP graphs."""
+        self._check(lib().lbm_batch_step(self._h, int(n)))
+
+    def step_eager(self, n=1):
+        self._check(lib().lbm_batch_step_eager(self._h, int(n)))
+
+    def profile_steps(self, n):
+        f, b = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().lbm_batch_profile_steps(self._h, int(n), ctypes.byref(f), ctypes.byref(b)))
+        return {"fluid_ms": f.value, "boundary_ms": b.value, "steps": int(n)}
+
+    def synchronize(self):
+        self._check(lib().lbm_batch_synchronize(self._h))
+
+    @property
+    def step_count(self):
+        t = ctypes.c_uint64()
+        self._check(lib().lbm_batch_get_step_count(self._h, ctypes.byref(t)))
+        return t.value
+
+    @step_count.setter
+    def step_count(self, t):
+        self._check(lib().lbm_batch_set_step_count(self._h, int(t)))
+
+    def boundary_counts(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().lbm_batch_boundary_counts(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def memory_bytes(self):
+        s, t = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(lib().lbm_batch_memory_bytes(self._h, ctypes.byref(s), ctypes.byref(t)))
+        return s.value, t.value
+
+    def check(self):
+        bad = ctypes.c_uint64()
+        st = lib().lbm_batch_check(self._h, ctypes.byref(bad))
+        if st not in (OK, ERR_UNSTABLE):
+            self._check(st)
+        return bad.value
+
+    def tuning(self):
+        t = BatchTuning()
+        self._check(lib().lbm_batch_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, block, wg_per_cu=1):
+        self._check(lib().lbm_batch_set_tuning(self._h, int(block), int(wg_per_cu)))
+
+    def tune(self, cache=None):
+        t = BatchTuning()
+        self._check(lib().lbm_batch_tune(self._h, None if cache is None else str(cache).encode(), ctypes.byref(t)))
+        return t.as_dict()
 
 
 def _torch_stream():

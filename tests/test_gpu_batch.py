@@ -1,0 +1,179 @@
+"""GPU parity of the batched step: every domain of a mixed batch against the
+FP64 oracle (FP32 within 1e-5 per moment group; Q16 codes within 1 LSB, < 1%
+differing), agreement with the single-domain API (FP32 within 1e-6 per group:
+the two kernels may round in a different order; Q16 codes within 1 LSB at
+fewer than 1e-4 of them), graph
+replays equal to eager launches, and results independent of the work split."""
+import numpy as np
+import pytest
+
+from helpers import group_rel_err, unpack
+from paper_2602_05295_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# whole-plane strips, halo strips (100 x 37, 64 x 64), tiny and single-cell domains
+DIMS = [(20, 30, 7), (100, 37, 9), (3, 5, 2), (1, 1, 1), (64, 64, 5), (33, 17, 12)]
+TAUS = [0.6, 0.55, 0.7, 0.8, 0.52, 0.65]
+
+
+def _note(*a):
+    print("CASE", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2602_05295_amd import homelbm
+    homelbm.lib()
+    return homelbm
+
+
+def _masks():
+    out = []
+    for k, d in enumerate(DIMS):
+        if k in (0, 1, 5):
+            out.append(W.sphere_mask(*d, phi=0.08, rmin=1.5, rmax=3.0, seed=10 + k))
+        else:
+            out.append(None)
+    return out
+
+
+def _moments(k, d):
+    return W.random_moments(*d, seed=40 + k, dj=0.02, dp=0.003).astype(np.float32)
+
+
+def test_batch_fp32_matches_oracle(H, orc):
+    _note("batch fp32 vs oracle", DIMS)
+    masks = _masks()
+    with H.HomeLBMBatch(DIMS, TAUS, masks, fmt="fp32") as b:
+        m0 = []
+        for k, d in enumerate(DIMS):
+            b.set_moments(k, _moments(k, d))
+            m0.append(b.get_moments(k).astype(np.float64))
+        b.step(2)
+        got = [b.get_moments(k) for k in range(len(DIMS))]
+    for k, d in enumerate(DIMS):
+        P = orc.make_params(d, TAUS[k])
+        ref = orc.step(P, orc.step(P, m0[k], masks[k]), masks[k])
+        err = group_rel_err(got[k], ref)
+        assert max(err.values()) <= 1e-5, (k, d, err)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_q16_codes_match_oracle(H, orc, mode):
+    _note("batch q16 vs oracle", mode)
+    masks = _masks()
+    seed, t0 = 9, 5
+    with H.HomeLBMBatch(DIMS, TAUS, masks, fmt="q16") as b:
+        b.set_options(dither_mode=mode, seed=seed)
+        for k, d in enumerate(DIMS):
+            b.set_moments(k, _moments(k, d))
+        b.step_count = t0
+        w0 = [b.get_raw(k).copy() for k in range(len(DIMS))]
+        b.step(1)
+        got = [b.get_raw(k) for k in range(len(DIMS))]
+    for k, d in enumerate(DIMS):
+        P = orc.make_params(d, TAUS[k])
+        ref = orc.q16_step(P, w0[k], masks[k], t=t0, seed=seed, mode=mode)
+        diff = np.abs(unpack(got[k]) - unpack(ref))
+        if masks[k] is not None:
+            diff = diff[:, masks[k] == 0]
+        assert diff.max() <= 1, (k, d, diff.max())
+        assert (diff > 0).mean() < 0.01, (k, d, (diff > 0).mean())
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_batch_equals_single_domain(H, fmt):
+    _note("batch vs single", fmt)
+    masks = _masks()
+    with H.HomeLBMBatch(DIMS, TAUS, masks, fmt=fmt) as b:
+        b.set_options(dither_mode=1, seed=4)
+        for k, d in enumerate(DIMS):
+            b.set_moments(k, _moments(k, d))
+        b.step(3)
+        got = [b.get_raw(k) for k in range(len(DIMS))]
+    for k, d in enumerate(DIMS):
+        with H.HomeLBM(d, TAUS[k], mask=masks[k], fmt=fmt) as s:
+            s.set_options(dither_mode=1, seed=4)
+            s.set_moments(_moments(k, d))
+            s.step(3)
+            ref = s.get_raw()
+        if fmt == "q16":
+            diff = np.abs(unpack(got[k]) - unpack(ref))
+            assert diff.max() <= 1 and (diff > 0).mean() < 1e-4, (k, d)
+        else:
+            g = got[k].astype(np.float64)
+            r = ref.astype(np.float64)
+            g[0] += 1.0
+            r[0] += 1.0
+            err = group_rel_err(g, r)
+            assert max(err.values()) <= 1e-6, (k, d, err)
+
+
+def test_graph_replays_match_eager_launches(H):
+    _note("batch graph replays")
+    masks = _masks()
+    outs = {}
+    for how in ("graph", "eager"):
+        with H.HomeLBMBatch(DIMS, TAUS, masks, fmt="q16") as b:
+            b.set_options(dither_mode=1, seed=2)
+            for k, d in enumerate(DIMS):
+                b.set_moments(k, _moments(k, d))
+            states = []
+            for rep in range(4):
+                if how == "graph":
+                    b.step(5)   # the same captured 5-step sequence, replayed
+                else:
+                    b.step_eager(5)
+                b.synchronize()
+                states.append([b.get_raw(k).copy() for k in range(len(DIMS))])
+                # eager work between replays
+                b.check()
+            outs[how] = states
+            assert b.step_count == 20
+    for rep in range(4):
+        for k in range(len(DIMS)):
+            assert np.array_equal(outs["graph"][rep][k], outs["eager"][rep][k]), (rep, k)
+
+
+def test_work_split_does_not_change_results(H, tmp_path):
+    _note("batch tuning")
+    dims = [(20, 30, 7), (64, 64, 5), (33, 17, 12), (80, 21, 6)]
+    taus = [0.6, 0.52, 0.65, 0.7]
+    res = {}
+    with H.HomeLBMBatch(dims, taus, fmt="q16") as b:
+        for k, d in enumerate(dims):
+            b.set_moments(k, _moments(k, d))
+        raw0 = [b.get_raw(k).copy() for k in range(len(dims))]
+        for block, wgpc in ((256, 1), (256, 4), (512, 2), (1024, 1)):
+            b.set_tuning(block, wgpc)
+            for k in range(len(dims)):
+                b.set_raw(k, raw0[k])
+            b.step_count = 0
+            b.step(2)
+            res[(block, wgpc)] = [b.get_raw(k).copy() for k in range(len(dims))]
+        cache = tmp_path / "tune.json"
+        t1 = b.tune(cache)
+        assert t1["from_cache"] == 0 and t1["block"] in (256, 512, 1024) and t1["fluid_ms"] > 0
+    with H.HomeLBMBatch(dims, taus, fmt="q16") as b2:
+        t2 = b2.tune(cache)
+        assert t2["from_cache"] == 1 and (t2["block"], t2["wg_per_cu"]) == (t1["block"], t1["wg_per_cu"])
+    ref = res[(1024, 1)]
+    for key, states in res.items():
+        for k in range(len(dims)):
+            assert np.array_equal(states[k], ref[k]), (key, k)
+
+
+def test_batch_invalid_use(H):
+    _note("batch invalid use")
+    with H.HomeLBMBatch([(8, 8, 8)], [0.6], fmt="fp32") as b:
+        with pytest.raises(H.LBMError):
+            b.get_moments(1)
+        with pytest.raises(H.LBMError):
+            b.set_tuning(384, 1)
+        with pytest.raises(H.LBMError):
+            b.set_tuning(1024, 64)
+        o = b.options()
+        o.inflow = 1
+        import ctypes
+        assert H.lib().lbm_batch_set_options(b._h, ctypes.byref(o)) == H.ERR_UNSUPPORTED
