@@ -7,14 +7,13 @@
 // projection, the shift reversed, adjoint of the reconstruction) followed by
 // the per-cell transpose of A' (lbm_device.h, coeffs_T).  The boundary pass
 // overwrote the listed cells, so the fluid adjoint reads lam(t+1) as zero
-// there and at solid cells; the boundary adjoint then sends every link of a
-// listed cell to its actual source (bounce-back to the cell itself, inflow
-// through the inflow coefficients, outflow to the face cell, other links to
-// x - c_i), adding with float atomics.
+// there and at solid cells; the boundary adjoint then gathers, for every cell
+// a listed cell reads, the adjoint of what was read (adjoint_gather_kernel).
 //
-// The fluid adjoint uses the forward pass's tiling: 64 x 13 tiles, y pass
-// first (the halo rows only load and take the first transposed projection),
-// x pass with the halo-column wavefront, z pass in a register window.
+// The fluid adjoint uses the forward pass's tiling and work split (64-wide
+// tiles of 8 or 13 rows, phase-aligned z segments): y pass first (the halo
+// rows only load and take the first transposed projection), x pass with the
+// halo-column wavefront, z pass in a register window.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -23,12 +22,10 @@ namespace lbm {
 namespace {
 
 constexpr int RW = 64;
-constexpr int TYR = 13;
-constexpr int NRW = TYR + 2;
-constexpr int NTH = (NRW + 1) * RW;
 
+template <int TYR>
 struct AdjLds {
-  float ly[9][NRW][RW];      // y movers of 6 groups (9 values: 3 groups carry one value)
+  float ly[9][TYR + 2][RW];   // y movers of 6 groups (9 values: 3 groups carry one value)
   float lyc[9][2][16];
   float lx[15][TYR][RW + 2];  // x movers of 9 groups (15 values)
 };
@@ -42,8 +39,11 @@ __device__ inline void load10(const float* const p[10], uint32_t cell, float v[1
 
 }  // namespace
 
-__global__ void __launch_bounds__(NTH) adjoint_fluid_kernel(AdjParams a, int ntx, int nty, int nwg) {
-  __shared__ AdjLds L;
+template <int TYR>
+__global__ void __launch_bounds__((TYR + 3) * RW) adjoint_fluid_kernel(AdjParams a, int ntx, int nty, int nseg,
+                                                                       int nwg) {
+  constexpr int NRW = TYR + 2;
+  __shared__ AdjLds<TYR> L;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
   const bool colw = wave == NRW;
@@ -62,18 +62,15 @@ __global__ void __launch_bounds__(NTH) adjoint_fluid_kernel(AdjParams a, int ntx
   const bool inner = r >= 1 && r <= TYR;
   const bool compute = !colw && inner;
 
-  const int b = int(blockIdx.x);
-  const int lb = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
-  const uint64_t W = uint64_t(ntx) * uint64_t(nty) * uint64_t(nz);
-  uint64_t w = W * uint64_t(lb) / uint64_t(nwg);
-  const uint64_t wend = W * uint64_t(lb + 1) / uint64_t(nwg);
+  const int ntiles = ntx * nty;
+  const int items = ntiles * nseg;
   const uint32_t plane = uint32_t(nx) * uint32_t(ny);
 
-  while (w < wend) {
-    const int t = int(w / uint64_t(nz));
-    const int za = int(w % uint64_t(nz));
-    const int zb = int(min(uint64_t(nz), uint64_t(za) + (wend - w)));
-    w += uint64_t(zb - za);
+  // the same phase-aligned, XCD-grouped (tile, z segment) items as the forward pass
+  for (int q = xcd_logical_block(int(blockIdx.x), nwg); q < items; q += nwg) {
+    const int t = q % ntiles, sg = q / ntiles;
+    const int za = int(int64_t(nz) * sg / nseg);
+    const int zb = int(int64_t(nz) * (sg + 1) / nseg);
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
     const int xw = wrapi(gx, nx), yw = wrapi(gy, ny);
@@ -83,11 +80,26 @@ __global__ void __launch_bounds__(NTH) adjoint_fluid_kernel(AdjParams a, int ntx
     float w0[8], wm1[8], wm2[8];  // z window: G0 of the previous plane, G- of the previous two
 #pragma unroll
     for (int g = 0; g < 8; ++g) w0[g] = wm1[g] = wm2[g] = 0.0f;
+    // the next plane's adjoint input and flag in flight while this one is computed
+    float gn[10];
+    uint8_t fn;
+    {
+      const uint32_t c0 = row + plane * uint32_t(wrap1(za - 1, nz));
+      load10(a.lam_in, c0, gn);
+      fn = a.flags[c0];
+    }
+    uint8_t fprev = 0;  // flag of plane p - 1
     for (int p = za - 1; p <= zb; ++p) {
-      const uint32_t cell = row + plane * uint32_t(wrap1(p, nz));
       float g[10];
-      load10(a.lam_in, cell, g);
-      if (a.flags[cell] != 0) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) g[k] = gn[k];
+      const uint8_t fl = fn;
+      if (p + 1 <= zb) {
+        const uint32_t c1 = row + plane * uint32_t(wrap1(p + 1, nz));
+        load10(a.lam_in, c1, gn);
+        fn = a.flags[c1];
+      }
+      if (fl != 0) {
 #pragma unroll
         for (int k = 0; k < 10; ++k) g[k] = 0.0f;
       }
@@ -218,7 +230,7 @@ __global__ void __launch_bounds__(NTH) adjoint_fluid_kernel(AdjParams a, int ntx
             float out[10];
 #pragma unroll
             for (int k = 0; k < 10; ++k) out[k] = 0.0f;
-            if (a.flags[qc] != 2) {
+            if (fprev != 2) {
               const CellLin cl = cell_lin(mq, a.om1, nullptr);
               coeffs_T(cl, a.om1, gA, true, out);
             }
@@ -233,6 +245,7 @@ __global__ void __launch_bounds__(NTH) adjoint_fluid_kernel(AdjParams a, int ntx
           w0[q] = Z0[q];
         }
       }
+      fprev = fl;
     }
   }
 }
@@ -277,68 +290,150 @@ __device__ inline void add_basis(float gf, int cx, int cy, int cz, float gA[NA])
   gA[A111] += gf * px[1] * py[1] * pz[1];
 }
 
-__device__ inline void scatter_T(const AdjParams& a, uint32_t s, const float gA[NA], const float* uin) {
+// gf = d(new moments of a cell)/d f_i . g for link c = (cx, cy, cz)
+__device__ inline float link_dot(const float g[10], int cx, int cy, int cz) {
+  const float fx = float(cx), fy = float(cy), fz = float(cz);
+  float gf = g[0] + fx * g[1] + fy * g[2] + fz * g[3];
+  gf = fmaf(fx * fx - R3, g[4], gf);
+  gf = fmaf(fy * fy - R3, g[5], gf);
+  gf = fmaf(fz * fz - R3, g[6], gf);
+  gf = fmaf(fx * fy, g[7], gf);
+  gf = fmaf(fx * fz, g[8], gf);
+  gf = fmaf(fy * fz, g[9], gf);
+  return gf;
+}
+
+// Boundary adjoint as a gather, one thread per source cell s (a fluid cell
+// that some listed fluid cell reads, or a listed fluid cell itself).  s
+// collects, from every listed fluid cell t it feeds, the adjoint of the
+// distribution t took from it:
+//   - regular pulls: t = s + c_i reads f+_i(s);
+//   - outflow (zero gradient): s on the outflow face feeds the face cell
+//     t = s + (0, c_y, c_z) on link (-1, c_y, c_z);
+//   - s's own links when s is listed: bounce-back links read f+_opp(i)(s);
+//     inflow links read the inflow coefficients of s (their own Jacobian).
+// Link types follow from the flags and the faces alone, so no per-link data
+// is stored.  The sum goes through one transposed Jacobian of s and is added
+// to what the fluid adjoint wrote for s (one writer per cell, no atomics).
+__global__ void __launch_bounds__(256) adjoint_gather_kernel(AdjParams a, const uint32_t* __restrict__ src, int count) {
+  const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const bool open_x = a.g.inflow != 0;
+  const uint32_t s = src[e];
+  const int x = int(s % uint32_t(nx));
+  const int y = int((s / uint32_t(nx)) % uint32_t(ny));
+  const int z = int(s / (uint32_t(nx) * uint32_t(ny)));
+  const bool listed = a.flags[s] == 1;
+  const bool in_face = open_x && x == 0;
+  const bool out_face = open_x && x == nx - 1;
+  float gown[10];
+  if (listed) load10(a.lam_in, s, gown);
+  float gA[NA], gin[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) gA[k] = gin[k] = 0.0f;
+  bool any_in = false;
+  for (int i = 0; i < 27; ++i) {
+    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    const uint32_t yz_up = uint32_t(nx) * (uint32_t(wrapi(y + cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z + cz, nz)));
+    // regular pull by t = s + c
+    int tx = x + cx;
+    bool valid = true;
+    if (open_x)
+      valid = tx >= 0 && tx < nx;
+    else
+      tx = wrapi(tx, nx);
+    if (valid) {
+      const uint32_t t = uint32_t(tx) + yz_up;
+      if (a.flags[t] == 1) {
+        float g[10];
+        load10(a.lam_in, t, g);
+        add_basis(link_dot(g, cx, cy, cz), cx, cy, cz, gA);
+      }
+    }
+    // zero-gradient outflow: t = s + (0, c_y, c_z) on the face reads s on link (-1, c_y, c_z)
+    if (out_face && cx == -1) {
+      const uint32_t t = uint32_t(x) + yz_up;
+      float g[10];
+      load10(a.lam_in, t, g);
+      add_basis(link_dot(g, cx, cy, cz), cx, cy, cz, gA);
+    }
+    // own links of a listed cell
+    if (listed) {
+      if (in_face && cx == 1) {
+        add_basis(link_dot(gown, cx, cy, cz), cx, cy, cz, gin);
+        any_in = true;
+      } else if (!(out_face && cx == -1)) {
+        int sx = x - cx;
+        bool inside = true;
+        if (open_x)
+          inside = sx >= 0 && sx < nx;
+        else
+          sx = wrapi(sx, nx);
+        if (inside) {
+          const uint32_t q =
+              uint32_t(sx) + uint32_t(nx) * (uint32_t(wrapi(y - cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z - cz, nz)));
+          if (a.flags[q] == 2) add_basis(link_dot(gown, cx, cy, cz), -cx, -cy, -cz, gA);  // bounce-back
+        }
+      }
+    }
+  }
   float m[10];
   load10(a.m, s, m);
-  const CellLin cl = cell_lin(m, a.om1, uin);
   float out[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) out[k] = 0.0f;
-  coeffs_T(cl, a.om1, gA, uin == nullptr, out);
+  {
+    const CellLin cl = cell_lin(m, a.om1, nullptr);
+    coeffs_T(cl, a.om1, gA, true, out);
+  }
+  if (any_in) {
+    const CellLin cl = cell_lin(m, a.om1, a.u_in);
+    coeffs_T(cl, a.om1, gin, false, out);
+  }
 #pragma unroll
-  for (int k = 0; k < 10; ++k) atomicAdd(&a.lam_out[k][s], out[k]);
+  for (int k = 0; k < 10; ++k) a.lam_out[k][s] += out[k];
 }
 
-__global__ void __launch_bounds__(256) adjoint_boundary_kernel(AdjParams a, const uint32_t* __restrict__ cells,
-                                                               const uint32_t* __restrict__ bits, int count) {
-  const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= count) return;
-  const uint32_t b = bits[e];
-  if (b & BIT_SOLID) return;
-  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const uint32_t cell = cells[e];
-  const int x = int(cell % uint32_t(nx));
-  const int y = int((cell / uint32_t(nx)) % uint32_t(ny));
-  const int z = int(cell / (uint32_t(nx) * uint32_t(ny)));
-  float g[10];
-  load10(a.lam_in, cell, g);
-  float gself[NA], gin[NA];
-#pragma unroll
-  for (int k = 0; k < NA; ++k) gself[k] = gin[k] = 0.0f;
-  for (int i = 0; i < 27; ++i) {
-    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-    const float fx = float(cx), fy = float(cy), fz = float(cz);
-    // d(new moments)/d f_i . g
-    float gf = g[0] + fx * g[1] + fy * g[2] + fz * g[3];
-    gf = fmaf(fx * fx - R3, g[4], gf);
-    gf = fmaf(fy * fy - R3, g[5], gf);
-    gf = fmaf(fz * fz - R3, g[6], gf);
-    gf = fmaf(fx * fy, g[7], gf);
-    gf = fmaf(fx * fz, g[8], gf);
-    gf = fmaf(fy * fz, g[9], gf);
-    if ((b & BIT_INFLOW) && cx == 1) {
-      add_basis(gf, cx, cy, cz, gin);
-    } else if ((b & BIT_OUTFLOW) && cx == -1) {
-      const uint32_t s = uint32_t(nx - 1) + uint32_t(nx) * (uint32_t(wrapi(y - cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z - cz, nz)));
-      float gA[NA];
-#pragma unroll
-      for (int k = 0; k < NA; ++k) gA[k] = 0.0f;
-      add_basis(gf, cx, cy, cz, gA);
-      scatter_T(a, s, gA, nullptr);
-    } else if ((b >> i) & 1u) {
-      add_basis(gf, -cx, -cy, -cz, gself);
-    } else {
-      const uint32_t s = uint32_t(wrapi(x - cx, nx)) +
-                         uint32_t(nx) * (uint32_t(wrapi(y - cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z - cz, nz)));
-      float gA[NA];
-#pragma unroll
-      for (int k = 0; k < NA; ++k) gA[k] = 0.0f;
-      add_basis(gf, cx, cy, cz, gA);
-      scatter_T(a, s, gA, nullptr);
+// Source cells of the gather: fluid cells that are listed or feed a listed
+// fluid cell (by a regular pull or the outflow rule).  Compacted with one
+// atomic per wavefront; counter[0] receives the count.
+__global__ void __launch_bounds__(256) adjoint_sources_kernel(const uint8_t* __restrict__ flags, Geometry g,
+                                                              uint32_t* counter, uint32_t* list, uint32_t capacity) {
+  const uint32_t N = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(g.nz);
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  bool keep = false;
+  if (s < N && flags[s] != 2) {
+    keep = flags[s] == 1;
+    const int x = int(s % uint32_t(g.nx));
+    const int y = int((s / uint32_t(g.nx)) % uint32_t(g.ny));
+    const int z = int(s / (uint32_t(g.nx) * uint32_t(g.ny)));
+    for (int i = 0; i < 27 && !keep; ++i) {
+      const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+      int tx = x + cx;
+      if (g.inflow) {
+        if (tx < 0 || tx >= g.nx) continue;
+      } else {
+        tx = wrapi(tx, g.nx);
+      }
+      const uint32_t t =
+          uint32_t(tx) + uint32_t(g.nx) * (uint32_t(wrapi(y + cy, g.ny)) + uint32_t(g.ny) * uint32_t(wrapi(z + cz, g.nz)));
+      keep = flags[t] == 1;
     }
   }
-  scatter_T(a, cell, gself, nullptr);
-  if (b & BIT_INFLOW) scatter_T(a, cell, gin, a.u_in);
+  const unsigned long long vote = __ballot(keep);
+  if (vote == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll(static_cast<long long>(vote)) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, uint32_t(__popcll(vote)));
+  if (list == nullptr) return;
+  base = __shfl(base, leader);
+  if (keep) {
+    const unsigned long long below = lane == 0 ? 0ull : (vote & ((~0ull) >> (64 - lane)));
+    const uint32_t k = base + uint32_t(__popcll(below));
+    if (k < capacity) list[k] = s;
+  }
 }
 
 // flags: 1 = listed fluid cell, 2 = solid cell, 0 = other fluid cell
@@ -393,19 +488,27 @@ int cus() {
 }
 }  // namespace
 
-hipError_t launch_adjoint(const AdjParams& p, const uint32_t* cells, const uint32_t* bits, int count,
-                          hipStream_t s) {
-  const int ntx = (p.g.nx + RW - 1) / RW;
-  const int nty = (p.g.ny + TYR - 1) / TYR;
-  const uint64_t W = uint64_t(ntx) * uint64_t(nty) * uint64_t(p.g.nz);
-  uint64_t n = uint64_t(cus());
-  const uint64_t cap = (W + 7) / 8;
-  if (n > cap) n = cap;
-  if (n < 1) n = 1;
-  hipLaunchKernelGGL(adjoint_fluid_kernel, dim3(uint32_t(n)), dim3(NTH), 0, s, p, ntx, nty, int(n));
+hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* src, int nsrc, hipStream_t s) {
+  // the forward pass's split at one of the two compiled tile heights (8 unless
+  // 13 is asked for: the 13-row tile needs more registers than fit)
+  const FluidPlan c = fluid_plan(p.g, rows == 13 ? 13 : 8, cus());
+  if (c.rows == 8)
+    hipLaunchKernelGGL(adjoint_fluid_kernel<8>, dim3(uint32_t(c.nwg)), dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+                       c.nwg);
+  else
+    hipLaunchKernelGGL(adjoint_fluid_kernel<13>, dim3(uint32_t(c.nwg)), dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+                       c.nwg);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || count <= 0) return e;
-  hipLaunchKernelGGL(adjoint_boundary_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, cells, bits, count);
+  if (e != hipSuccess || nsrc <= 0) return e;
+  hipLaunchKernelGGL(adjoint_gather_kernel, dim3((nsrc + 255) / 256), dim3(256), 0, s, p, src, nsrc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_sources(const uint8_t* flags, const Geometry& g, uint32_t* counter, uint32_t* list,
+                                  uint32_t capacity, hipStream_t s) {
+  const uint64_t N = uint64_t(g.nx) * g.ny * g.nz;
+  hipLaunchKernelGGL(adjoint_sources_kernel, dim3(uint32_t((N + 255) / 256)), dim3(256), 0, s, flags, g, counter,
+                     list, capacity);
   return hipGetLastError();
 }
 
