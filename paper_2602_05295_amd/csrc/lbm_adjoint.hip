@@ -252,7 +252,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) adjoint_fluid_kernel(AdjParams
 
 // --------------------------------------------------------- boundary adjoint ---
 
-// basis values P_n(c) in the index scaling of hermite_coeffs (see eval_dir)
+// basis values P_n(c) in the index scaling of hermite_coeffs (as in eval_link)
 __device__ inline void basis1_adj(int c, float P[3]) {
   if (c == 0) {
     P[0] = C0;

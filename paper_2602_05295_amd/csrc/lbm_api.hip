@@ -29,6 +29,7 @@ struct lbm_ctx {
   uint8_t* d_mask = nullptr;          // copy of the solid mask (nullptr: no solids)
   uint32_t* d_cells = nullptr;        // boundary list
   uint32_t* d_bits = nullptr;
+  uint32_t* d_yz = nullptr;           // y | z << 16 of the fluid entries
   int64_t n_fluid_b = 0, n_solid_b = 0;
   uint32_t* d_counters = nullptr;     // 3 list counters
   unsigned long long* d_bad = nullptr;
@@ -72,7 +73,8 @@ Geometry geom(const lbm_ctx* c) { return Geometry{c->nx, c->ny, c->nz, c->opt.in
 void free_list(lbm_ctx* c) {
   if (c->d_cells) (void)hipFree(c->d_cells);
   if (c->d_bits) (void)hipFree(c->d_bits);
-  c->d_cells = c->d_bits = nullptr;
+  if (c->d_yz) (void)hipFree(c->d_yz);
+  c->d_cells = c->d_bits = c->d_yz = nullptr;
   c->n_fluid_b = c->n_solid_b = 0;
   c->list_built = false;
   c->flags_valid = false;
@@ -90,9 +92,9 @@ int build_list(lbm_ctx* c) {
     c->list_inflow = g.inflow;
     return LBM_OK;
   }
-  hipError_t e = hipMemsetAsync(c->d_counters, 0, 3 * sizeof(uint32_t), c->stream);
+  hipError_t e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(uint32_t), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync(counters)");
-  e = launch_classify(c->d_mask, g, c->d_counters, nullptr, nullptr, 0, c->stream);
+  e = launch_classify(c->d_mask, g, c->d_counters, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "classify (count)");
   uint32_t cnt[3] = {0, 0, 0};
   e = hipMemcpyAsync(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
@@ -102,9 +104,13 @@ int build_list(lbm_ctx* c) {
   if (total > 0) {
     e = hipMalloc(&c->d_cells, size_t(total) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_bits, size_t(total) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_yz, size_t(std::max<uint32_t>(cnt[0], 1)) * 4);
     if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(boundary list)");
-    e = hipMemsetAsync(c->d_counters, 0, 3 * sizeof(uint32_t), c->stream);
-    if (e == hipSuccess) e = launch_classify(c->d_mask, g, c->d_counters, c->d_cells, c->d_bits, uint32_t(total), c->stream);
+    // fluid entries first, solid entries after them
+    e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(uint32_t), c->stream);
+    if (e == hipSuccess)
+      e = launch_classify(c->d_mask, g, c->d_counters, c->d_cells, c->d_bits, c->d_yz, cnt[0], c->d_cells + cnt[0],
+                          c->d_bits + cnt[0], cnt[1], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "classify (fill)");
   }
@@ -154,7 +160,9 @@ int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
   const int64_t n = c->n_fluid_b + c->n_solid_b;
   if (n > 0) {
     if (ev) e = hipEventRecord(ev[2], c->stream);
-    if (e == hipSuccess) e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, int(n), c->stream);
+    if (e == hipSuccess)
+      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, int(c->n_fluid_b), int(c->n_solid_b),
+                          c->stream);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
@@ -436,7 +444,9 @@ int lbm_memory_bytes(const lbm_ctx* c, size_t* sb, size_t* tb) {
   if (!c) return LBM_ERR_INVALID_ARG;
   const size_t s = 2 * state_bytes(c);
   if (sb) *sb = s;
-  if (tb) *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + 4 * 4 + 8;
+  if (tb)
+    *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 4 +
+          4 * 4 + 8;
   return LBM_OK;
 }
 

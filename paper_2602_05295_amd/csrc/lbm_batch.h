@@ -45,8 +45,9 @@ extern const int kBatchBlocks[3];
 size_t batch_fluid_lds(int block);
 
 hipError_t launch_batch_fluid(int fmt, int block, const BatchStepParams& p, hipStream_t s);
+// Boundary pass: nfluid fluid entries, then nsolid solid entries (at + nfluid).
 hipError_t launch_batch_boundary(int fmt, const BatchStepParams& p, const uint32_t* cells, const uint32_t* bits,
-                                 const uint16_t* dom, int count, hipStream_t s);
+                                 const uint32_t* yz, const uint16_t* dom, int nfluid, int nsolid, hipStream_t s);
 hipError_t launch_step_advance(uint32_t* step, uint32_t n, hipStream_t s);
 // Blocks of the strip kernel that fit on one CU (0 on error).
 int batch_fluid_occupancy(int fmt, int block);

@@ -209,15 +209,9 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
   }
 }
 
-// One listed cell per thread; the domain's planes are the batch planes offset
-// by the domain's first cell.
+// The domain's planes are the batch planes offset by the domain's first cell.
 template <int FMT>
-__global__ void __launch_bounds__(256) batch_boundary_kernel(BatchStepParams a, const uint32_t* __restrict__ cells,
-                                                             const uint32_t* __restrict__ bits,
-                                                             const uint16_t* __restrict__ dom, int count) {
-  const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= count) return;
-  const BatchDomain D = a.doms[dom[e]];
+__device__ inline StepParams domain_params(const BatchStepParams& a, const BatchDomain& D) {
   StepParams p{};
   constexpr int NP = FMT == FMT_F32 ? 10 : 5;
 #pragma unroll
@@ -230,7 +224,29 @@ __global__ void __launch_bounds__(256) batch_boundary_kernel(BatchStepParams a, 
   const int mode = FMT == FMT_Q16 ? a.dither_mode : 0;
   p.key = dither_key(*a.step + a.step_offset, a.seed, mode);
   p.dither = mode != 0;
-  boundary_entry<FMT>(p, cells[e], bits[e]);
+  return p;
+}
+
+// Listed fluid cells: 32 lanes each, as in the single-domain boundary pass.
+template <int FMT>
+__global__ void __launch_bounds__(256) batch_boundary_fluid_kernel(BatchStepParams a, const uint32_t* __restrict__ cells,
+                                                                   const uint32_t* __restrict__ bits,
+                                                                   const uint32_t* __restrict__ yz,
+                                                                   const uint16_t* __restrict__ dom, int count) {
+  const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
+  const int e = t >> 5;
+  if (e >= count) return;  // whole 32-lane groups leave together
+  const StepParams p = domain_params<FMT>(a, a.doms[dom[e]]);
+  boundary_group<FMT>(p, cells[e], bits[e], yz[e], t & 31);
+}
+
+template <int FMT>
+__global__ void __launch_bounds__(256) batch_boundary_solid_kernel(BatchStepParams a, const uint32_t* __restrict__ cells,
+                                                                   const uint16_t* __restrict__ dom, int count) {
+  const int e = int(blockIdx.x) * 256 + int(threadIdx.x);
+  if (e >= count) return;
+  const StepParams p = domain_params<FMT>(a, a.doms[dom[e]]);
+  boundary_solid<FMT>(p, cells[e]);
 }
 
 __global__ void step_advance_kernel(uint32_t* step, uint32_t n) {
@@ -273,14 +289,27 @@ hipError_t launch_batch_fluid(int fmt, int block, const BatchStepParams& p, hipS
 }
 
 hipError_t launch_batch_boundary(int fmt, const BatchStepParams& p, const uint32_t* cells, const uint32_t* bits,
-                                 const uint16_t* dom, int count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  const dim3 block(256), grid((count + 255) / 256);
-  if (fmt == FMT_F32)
-    hipLaunchKernelGGL(batch_boundary_kernel<FMT_F32>, grid, block, 0, s, p, cells, bits, dom, count);
-  else
-    hipLaunchKernelGGL(batch_boundary_kernel<FMT_Q16>, grid, block, 0, s, p, cells, bits, dom, count);
-  return hipGetLastError();
+                                 const uint32_t* yz, const uint16_t* dom, int nfluid, int nsolid, hipStream_t s) {
+  if (nfluid > 0) {
+    const dim3 grid(uint32_t((int64_t(nfluid) * 32 + 255) / 256));
+    if (fmt == FMT_F32)
+      hipLaunchKernelGGL(batch_boundary_fluid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, dom, nfluid);
+    else
+      hipLaunchKernelGGL(batch_boundary_fluid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, dom, nfluid);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (nsolid > 0) {
+    const dim3 grid(uint32_t((nsolid + 255) / 256));
+    if (fmt == FMT_F32)
+      hipLaunchKernelGGL(batch_boundary_solid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells + nfluid, dom + nfluid,
+                         nsolid);
+    else
+      hipLaunchKernelGGL(batch_boundary_solid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells + nfluid, dom + nfluid,
+                         nsolid);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_step_advance(uint32_t* step, uint32_t n, hipStream_t s) {

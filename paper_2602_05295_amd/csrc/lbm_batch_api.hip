@@ -173,6 +173,7 @@ struct lbm_batch {
   uint8_t* d_mask = nullptr;    // concatenated masks (nullptr: no solids anywhere)
   uint32_t* d_cells = nullptr;  // boundary list: domain-local cell, flags, domain
   uint32_t* d_bits = nullptr;
+  uint32_t* d_yz = nullptr;     // y | z << 16 of the fluid entries
   uint16_t* d_dom = nullptr;
   int64_t n_fluid_b = 0, n_solid_b = 0;
   uint32_t* d_counters = nullptr;
@@ -285,7 +286,9 @@ int enqueue_steps(lbm_batch* b, int n, int src, hipStream_t s, hipEvent_t* ev) {
     if (e == hipSuccess) e = launch_batch_fluid(b->fmt, b->tuning.block, p, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[4 * k + 1], s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[4 * k + 2], s);
-    if (e == hipSuccess && nb > 0) e = launch_batch_boundary(b->fmt, p, b->d_cells, b->d_bits, b->d_dom, int(nb), s);
+    if (e == hipSuccess && nb > 0)
+      e = launch_batch_boundary(b->fmt, p, b->d_cells, b->d_bits, b->d_yz, b->d_dom, int(b->n_fluid_b),
+                                int(b->n_solid_b), s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[4 * k + 3], s);
   }
   if (e == hipSuccess && n > 0) e = launch_step_advance(b->d_step, uint32_t(n), s);
@@ -330,8 +333,10 @@ int build_lists(lbm_batch* b) {
     if (!b->has_mask[size_t(d)]) continue;
     const Geometry g{b->dims[3 * d], b->dims[3 * d + 1], b->dims[3 * d + 2], 0};
     uint32_t cnt[3] = {0, 0, 0};
-    e = hipMemsetAsync(b->d_counters, 0, 3 * sizeof(uint32_t), b->stream);
-    if (e == hipSuccess) e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->d_counters, nullptr, nullptr, 0, b->stream);
+    e = hipMemsetAsync(b->d_counters, 0, 4 * sizeof(uint32_t), b->stream);
+    if (e == hipSuccess)
+      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->d_counters, nullptr, nullptr, nullptr, 0, nullptr,
+                          nullptr, 0, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     nf[size_t(d)] = cnt[0];
@@ -344,22 +349,30 @@ int build_lists(lbm_batch* b) {
   b->n_fluid_b = 0;
   b->n_solid_b = 0;
   if (total == 0) return LBM_OK;
+  int64_t nf_all = 0;
+  for (int d = 0; d < b->count; ++d) nf_all += nf[size_t(d)];
   e = hipMalloc(&b->d_cells, size_t(total) * 4);
   if (e == hipSuccess) e = hipMalloc(&b->d_bits, size_t(total) * 4);
+  if (e == hipSuccess) e = hipMalloc(&b->d_yz, size_t(std::max<int64_t>(nf_all, 1)) * 4);
   if (e == hipSuccess) e = hipMalloc(&b->d_dom, size_t(total) * 2);
   if (e != hipSuccess) return bhip(b, e, "hipMalloc(boundary list)");
+  // all fluid entries first (domain by domain), then all solid entries
+  int64_t nf_total = 0;
+  for (int d = 0; d < b->count; ++d) nf_total += nf[size_t(d)];
   std::vector<uint16_t> hdom(static_cast<size_t>(total));
-  int64_t base = 0;
+  int64_t fbase = 0, sbase = nf_total;
   for (int d = 0; d < b->count && e == hipSuccess; ++d) {
-    const uint32_t n = nf[size_t(d)] + ns[size_t(d)];
-    if (n == 0) continue;
+    if (nf[size_t(d)] + ns[size_t(d)] == 0) continue;
     const Geometry g{b->dims[3 * d], b->dims[3 * d + 1], b->dims[3 * d + 2], 0};
-    e = hipMemsetAsync(b->d_counters, 0, 3 * sizeof(uint32_t), b->stream);
+    e = hipMemsetAsync(b->d_counters, 0, 4 * sizeof(uint32_t), b->stream);
     if (e == hipSuccess)
-      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->d_counters, b->d_cells + base, b->d_bits + base, n,
+      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->d_counters, b->d_cells + fbase, b->d_bits + fbase,
+                          b->d_yz + fbase, nf[size_t(d)], b->d_cells + sbase, b->d_bits + sbase, ns[size_t(d)],
                           b->stream);
-    std::fill(hdom.begin() + base, hdom.begin() + base + n, uint16_t(d));
-    base += n;
+    std::fill(hdom.begin() + fbase, hdom.begin() + fbase + nf[size_t(d)], uint16_t(d));
+    std::fill(hdom.begin() + sbase, hdom.begin() + sbase + ns[size_t(d)], uint16_t(d));
+    fbase += nf[size_t(d)];
+    sbase += ns[size_t(d)];
   }
   if (e == hipSuccess) e = hipMemcpyAsync(b->d_dom, hdom.data(), hdom.size() * 2, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -587,8 +600,8 @@ int lbm_batch_destroy(lbm_batch* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (int k = 0; k < 2; ++k)
     if (b->buf[k]) (void)hipFree(b->buf[k]);
-  void* ptrs[] = {b->d_mask, b->d_cells, b->d_bits, b->d_dom, b->d_counters, b->d_bad,
-                  b->d_step, b->d_doms,  b->d_segs, b->d_wg_first};
+  void* ptrs[] = {b->d_mask, b->d_cells, b->d_bits, b->d_yz,   b->d_dom,
+                  b->d_counters, b->d_bad, b->d_step, b->d_doms, b->d_segs, b->d_wg_first};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -822,6 +835,7 @@ int lbm_batch_memory_bytes(const lbm_batch* b, size_t* state_bytes, size_t* tota
   if (state_bytes) *state_bytes = s;
   if (total_bytes)
     *total_bytes = s + (b->d_mask ? size_t(b->N) : 0) + size_t(b->n_fluid_b + b->n_solid_b) * 10 +
+                   size_t(b->n_fluid_b) * 4 +
                    b->plan.segs.size() * sizeof(BatchSeg) + b->plan.wg_first.size() * 4 +
                    size_t(b->count) * sizeof(BatchDomain) + 32;
   return LBM_OK;

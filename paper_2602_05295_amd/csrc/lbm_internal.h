@@ -61,13 +61,16 @@ extern const int kFluidTileRows[4];
 FluidPlan fluid_plan(const Geometry& g, int rows, int cus);
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s);
 
-// Boundary pass over the compacted list.
-hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits, int count,
-                           hipStream_t s);
+// Boundary pass over the compacted list: nfluid fluid entries (with their
+// y | z << 16 in yz), then nsolid solid entries (cells + nfluid).
+hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
+                           const uint32_t* yz, int nfluid, int nsolid, hipStream_t s);
 
-// Boundary list: count pass (cells == nullptr) or fill pass.
-hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t* counters, uint32_t* cells,
-                           uint32_t* bits, uint32_t capacity, hipStream_t s);
+// Boundary list: count pass (cells_f == nullptr) or fill pass (fluid entries
+// to cells_f / bits_f / yz_f, solid entries to cells_s / bits_s).
+hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t* counters, uint32_t* cells_f,
+                           uint32_t* bits_f, uint32_t* yz_f, uint32_t cap_f, uint32_t* cells_s, uint32_t* bits_s,
+                           uint32_t cap_s, hipStream_t s);
 
 // Codec / initialisation / read-back.
 hipError_t launch_set_moments(int fmt, const float* m, void* const out[10], const uint8_t* mask, int64_t N,
