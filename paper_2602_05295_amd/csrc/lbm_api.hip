@@ -30,6 +30,11 @@ struct lbm_ctx {
   uint32_t* d_cells = nullptr;        // boundary list
   uint32_t* d_bits = nullptr;
   uint32_t* d_yz = nullptr;           // y | z << 16 of the fluid entries
+  unsigned long long* d_lmask = nullptr;  // listed fluid cells: bitmap, prefix counts, side buffer
+  uint32_t* d_lbase = nullptr;
+  uint4* d_lpack = nullptr;               // the two packed per word for the fluid and boundary passes
+  uint32_t* d_order = nullptr;            // boundary pass order of the fluid entries: face cells first
+  float* d_side = nullptr;
   int64_t n_fluid_b = 0, n_solid_b = 0;
   uint32_t* d_counters = nullptr;     // 3 list counters
   unsigned long long* d_bad = nullptr;
@@ -74,7 +79,16 @@ void free_list(lbm_ctx* c) {
   if (c->d_cells) (void)hipFree(c->d_cells);
   if (c->d_bits) (void)hipFree(c->d_bits);
   if (c->d_yz) (void)hipFree(c->d_yz);
-  c->d_cells = c->d_bits = c->d_yz = nullptr;
+  if (c->d_lmask) (void)hipFree(c->d_lmask);
+  if (c->d_lbase) (void)hipFree(c->d_lbase);
+  if (c->d_lpack) (void)hipFree(c->d_lpack);
+  if (c->d_order) (void)hipFree(c->d_order);
+  if (c->d_side) (void)hipFree(c->d_side);
+  c->d_cells = c->d_bits = c->d_yz = c->d_lbase = nullptr;
+  c->d_lmask = nullptr;
+  c->d_lpack = nullptr;
+  c->d_order = nullptr;
+  c->d_side = nullptr;
   c->n_fluid_b = c->n_solid_b = 0;
   c->list_built = false;
   c->flags_valid = false;
@@ -83,7 +97,9 @@ void free_list(lbm_ctx* c) {
   c->n_src = 0;
 }
 
-// Builds the boundary list on the device: count pass, exact allocation, fill pass.
+// Builds the boundary list on the device: count pass (counts and the bitmap
+// of listed fluid cells), prefix counts of the bitmap on the host, exact
+// allocation, fill pass.
 int build_list(lbm_ctx* c) {
   free_list(c);
   const Geometry g = geom(c);
@@ -92,27 +108,63 @@ int build_list(lbm_ctx* c) {
     c->list_inflow = g.inflow;
     return LBM_OK;
   }
-  hipError_t e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(uint32_t), c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync(counters)");
-  e = launch_classify(c->d_mask, g, c->d_counters, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, c->stream);
+  const size_t nchunks = size_t((c->N + 63) / 64);
+  hipError_t e = hipMalloc(&c->d_lmask, nchunks * 8);
+  if (e == hipSuccess) e = hipMalloc(&c->d_lbase, nchunks * 4);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_lmask, 0, nchunks * 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(uint32_t), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "boundary list setup");
+  e = launch_classify(c->d_mask, g, 0, c->d_counters, c->d_lmask, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      0, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "classify (count)");
-  uint32_t cnt[3] = {0, 0, 0};
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  std::vector<unsigned long long> hmask(nchunks);
   e = hipMemcpyAsync(cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hmask.data(), c->d_lmask, nchunks * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reading list counts");
+  std::vector<uint32_t> hbase(nchunks);
+  uint32_t run = 0;
+  for (size_t k = 0; k < nchunks; ++k) {
+    hbase[k] = run;
+    run += uint32_t(__builtin_popcountll(hmask[k]));
+  }
+  if (run != cnt[0]) return fail(c, LBM_ERR_DEVICE, "boundary list: bitmap and count disagree");
+  std::vector<uint4> hpack(nchunks);
+  for (size_t k = 0; k < nchunks; ++k)
+    hpack[k] = make_uint4(uint32_t(hmask[k]), uint32_t(hmask[k] >> 32), hbase[k], 0u);
+  e = hipMemcpy(c->d_lbase, hbase.data(), nchunks * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_lpack, nchunks * sizeof(uint4));
+  if (e == hipSuccess) e = hipMemcpy(c->d_lpack, hpack.data(), nchunks * sizeof(uint4), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "uploading list offsets");
   const int64_t total = int64_t(cnt[0]) + cnt[1];
   if (total > 0) {
     e = hipMalloc(&c->d_cells, size_t(total) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_bits, size_t(total) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_yz, size_t(std::max<uint32_t>(cnt[0], 1)) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->d_side, size_t(std::max<uint32_t>(cnt[0], 1)) * 40);
     if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(boundary list)");
-    // fluid entries first, solid entries after them
+    // fluid entries in raster order, solid entries after them
     e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(uint32_t), c->stream);
     if (e == hipSuccess)
-      e = launch_classify(c->d_mask, g, c->d_counters, c->d_cells, c->d_bits, c->d_yz, cnt[0], c->d_cells + cnt[0],
-                          c->d_bits + cnt[0], cnt[1], c->stream);
+      e = launch_classify(c->d_mask, g, 0, c->d_counters, c->d_lmask, c->d_lbase, c->d_cells, c->d_bits, c->d_yz,
+                          c->d_cells + cnt[0], c->d_bits + cnt[0], cnt[1], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "classify (fill)");
+    if (g.inflow && cnt[0] > 0) {
+      // face cells (nine changed links each, with loads) in wavefronts of their own
+      std::vector<uint32_t> hbits(cnt[0]), order;
+      order.reserve(cnt[0]);
+      e = hipMemcpy(hbits.data(), c->d_bits, size_t(cnt[0]) * 4, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(c, e, "reading list flags");
+      for (uint32_t k = 0; k < cnt[0]; ++k)
+        if (hbits[k] & (BIT_INFLOW | BIT_OUTFLOW)) order.push_back(k);
+      for (uint32_t k = 0; k < cnt[0]; ++k)
+        if (!(hbits[k] & (BIT_INFLOW | BIT_OUTFLOW))) order.push_back(k);
+      e = hipMalloc(&c->d_order, size_t(cnt[0]) * 4);
+      if (e == hipSuccess) e = hipMemcpy(c->d_order, order.data(), size_t(cnt[0]) * 4, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(c, e, "uploading the boundary order");
+    }
   }
   c->n_fluid_b = cnt[0];
   c->n_solid_b = cnt[1];
@@ -146,6 +198,7 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   p.dither = mode != 0;
   p.key = dither_key(uint32_t(c->t), c->opt.seed, mode);
   for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
+  if (c->n_fluid_b > 0) p.lc = ListedCells{c->d_lpack, c->d_side, uint32_t(c->n_fluid_b)};
   return p;
 }
 
@@ -161,8 +214,8 @@ int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
   if (n > 0) {
     if (ev) e = hipEventRecord(ev[2], c->stream);
     if (e == hipSuccess)
-      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, int(c->n_fluid_b), int(c->n_solid_b),
-                          c->stream);
+      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_b),
+                          int(c->n_solid_b), c->stream);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
@@ -423,6 +476,16 @@ int lbm_set_raw(lbm_ctx* c, const void* in, size_t bytes, int on_device) {
   if (bytes != state_bytes(c)) return fail(c, LBM_ERR_INVALID_ARG, "bytes must equal lbm_raw_bytes()");
   hipError_t e = hipMemcpyAsync(c->buf[c->cur], in, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                 c->stream);
+  if (e == hipSuccess && !c->list_built) {
+    const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  if (e == hipSuccess && c->n_solid_b > 0) {
+    // solid cells next to fluid hold the rest state at every step
+    StepParams p = step_params(c, c->buf[c->cur], c->buf[c->cur]);
+    e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b),
+                        c->stream);
+  }
   if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "set_raw");
   return LBM_OK;
@@ -445,8 +508,8 @@ int lbm_memory_bytes(const lbm_ctx* c, size_t* sb, size_t* tb) {
   const size_t s = 2 * state_bytes(c);
   if (sb) *sb = s;
   if (tb)
-    *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 4 +
-          4 * 4 + 8;
+    *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 44 +
+          (c->d_lmask ? size_t((c->N + 63) / 64) * 28 : 0) + 4 * 4 + 8;
   return LBM_OK;
 }
 

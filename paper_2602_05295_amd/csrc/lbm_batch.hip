@@ -119,9 +119,16 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
 
     BRaw<FMT> nxt1{};
     if (active) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(za - 1, nz))) * 4u);
+    const bool keep = own && a.lc.side != nullptr;  // listed cells to look for
+    uint4 lw = make_uint4(0, 0, 0, 0);              // packed bitmap word of the cell stored next
     for (int p = za - 1; p <= zb; ++p) {
       const BRaw<FMT> cur = nxt1;
       if (active && p + 1 <= zb) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(p + 1, nz))) * 4u);
+      const uint4 lw_cur = lw;
+      if (keep && p >= za && p < zb) {  // plane p is stored in the next iteration
+        const uint32_t gc = D.off + rowc + plane * uint32_t(p);
+        lw = a.lc.lpack[gc >> 6];
+      }
 
       float f0[8];
       if (active) {
@@ -196,6 +203,13 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
           if (own) {
             const uint32_t cell = rowc + plane * uint32_t(p - 1);
             bstore<FMT>(a, (D.off + cell) * 4u, cell, key, dith, dr, j, P);
+            const int slot = keep ? listed_slot_in(lw_cur, D.off + cell) : -1;
+            if (slot >= 0) {
+              // a listed cell: its unrounded moments go to its side-buffer slot
+              const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
+#pragma unroll
+              for (int k = 0; k < 10; ++k) a.lc.side[size_t(k) * a.lc.nside + uint32_t(slot)] = v[k];
+            }
           }
         }
 #pragma unroll
@@ -224,20 +238,21 @@ __device__ inline StepParams domain_params(const BatchStepParams& a, const Batch
   const int mode = FMT == FMT_Q16 ? a.dither_mode : 0;
   p.key = dither_key(*a.step + a.step_offset, a.seed, mode);
   p.dither = mode != 0;
+  p.lc = a.lc;
   return p;
 }
 
-// Listed fluid cells: 32 lanes each, as in the single-domain boundary pass.
+// Listed fluid cells: one lane each; entry e is slot e of the side buffer
+// (the list runs in global cell order, so a domain's entries are contiguous).
 template <int FMT>
 __global__ void __launch_bounds__(256) batch_boundary_fluid_kernel(BatchStepParams a, const uint32_t* __restrict__ cells,
                                                                    const uint32_t* __restrict__ bits,
                                                                    const uint32_t* __restrict__ yz,
                                                                    const uint16_t* __restrict__ dom, int count) {
-  const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
-  const int e = t >> 5;
-  if (e >= count) return;  // whole 32-lane groups leave together
+  const int e = int(blockIdx.x) * 256 + int(threadIdx.x);
+  if (e >= count) return;
   const StepParams p = domain_params<FMT>(a, a.doms[dom[e]]);
-  boundary_group<FMT>(p, cells[e], bits[e], yz[e], t & 31);
+  boundary_fix<FMT>(p, uint32_t(e), cells[e], bits[e], yz[e]);
 }
 
 template <int FMT>
@@ -291,7 +306,7 @@ hipError_t launch_batch_fluid(int fmt, int block, const BatchStepParams& p, hipS
 hipError_t launch_batch_boundary(int fmt, const BatchStepParams& p, const uint32_t* cells, const uint32_t* bits,
                                  const uint32_t* yz, const uint16_t* dom, int nfluid, int nsolid, hipStream_t s) {
   if (nfluid > 0) {
-    const dim3 grid(uint32_t((int64_t(nfluid) * 32 + 255) / 256));
+    const dim3 grid(uint32_t((nfluid + 255) / 256));
     if (fmt == FMT_F32)
       hipLaunchKernelGGL(batch_boundary_fluid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, dom, nfluid);
     else

@@ -175,6 +175,10 @@ struct lbm_batch {
   uint32_t* d_bits = nullptr;
   uint32_t* d_yz = nullptr;     // y | z << 16 of the fluid entries
   uint16_t* d_dom = nullptr;
+  unsigned long long* d_lmask = nullptr;  // listed fluid cells: bitmap, prefix counts, side buffer
+  uint32_t* d_lbase = nullptr;
+  uint4* d_lpack = nullptr;               // the two packed per word for the fluid and boundary passes
+  float* d_side = nullptr;
   int64_t n_fluid_b = 0, n_solid_b = 0;
   uint32_t* d_counters = nullptr;
   unsigned long long* d_bad = nullptr;
@@ -186,6 +190,7 @@ struct lbm_batch {
   int nwg = 0;
   HostPlan plan;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (steps, parity) -> replayable sequence
+  std::vector<int64_t> solid_first, solid_count;           // each domain's listed solid entries
   uint64_t t = 0;
   std::string err;
 };
@@ -241,6 +246,7 @@ BatchStepParams params(const lbm_batch* b, int src, uint32_t k) {
   p.seed = b->opt.seed;
   p.dither_mode = b->fmt == FMT_Q16 ? b->opt.dither_mode : 0;
   p.nwg = b->nwg;
+  if (b->n_fluid_b > 0) p.lc = ListedCells{b->d_lpack, b->d_side, uint32_t(b->n_fluid_b)};
   return p;
 }
 
@@ -326,48 +332,74 @@ int graph_for(lbm_batch* b, int n, hipGraphExec_t* out) {
   return LBM_OK;
 }
 
+// Boundary lists of all domains: per-domain count passes (counts and the
+// global bitmap of listed fluid cells), prefix counts on the host, one list
+// (fluid entries in global cell order, then solid entries) and the side
+// buffer the fluid pass fills for the listed fluid cells.
 int build_lists(lbm_batch* b) {
   std::vector<uint32_t> nf(size_t(b->count), 0), ns(size_t(b->count), 0);
-  hipError_t e = hipSuccess;
+  bool any = false;
+  for (int d = 0; d < b->count; ++d) any = any || b->has_mask[size_t(d)];
+  b->n_fluid_b = 0;
+  b->n_solid_b = 0;
+  if (!any) return LBM_OK;
+  const size_t nchunks = size_t((b->N + 63) / 64);
+  hipError_t e = hipMalloc(&b->d_lmask, nchunks * 8);
+  if (e == hipSuccess) e = hipMalloc(&b->d_lbase, nchunks * 4);
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_lmask, 0, nchunks * 8, b->stream);
   for (int d = 0; d < b->count && e == hipSuccess; ++d) {
     if (!b->has_mask[size_t(d)]) continue;
     const Geometry g{b->dims[3 * d], b->dims[3 * d + 1], b->dims[3 * d + 2], 0};
-    uint32_t cnt[3] = {0, 0, 0};
+    uint32_t cnt[4] = {0, 0, 0, 0};
     e = hipMemsetAsync(b->d_counters, 0, 4 * sizeof(uint32_t), b->stream);
     if (e == hipSuccess)
-      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->d_counters, nullptr, nullptr, nullptr, 0, nullptr,
-                          nullptr, 0, b->stream);
+      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->offs[size_t(d)], b->d_counters, b->d_lmask, nullptr,
+                          nullptr, nullptr, nullptr, nullptr, nullptr, 0, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     nf[size_t(d)] = cnt[0];
     ns[size_t(d)] = cnt[1];
   }
   if (e != hipSuccess) return bhip(b, e, "boundary list (count)");
-  int64_t total = 0;
-  for (int d = 0; d < b->count; ++d) total += int64_t(nf[size_t(d)]) + ns[size_t(d)];
+  int64_t nf_all = 0, total = 0;
+  for (int d = 0; d < b->count; ++d) {
+    nf_all += nf[size_t(d)];
+    total += int64_t(nf[size_t(d)]) + ns[size_t(d)];
+  }
   if (total > int64_t(INT32_MAX)) return bfail(b, LBM_ERR_UNSUPPORTED, "boundary list too long");
-  b->n_fluid_b = 0;
-  b->n_solid_b = 0;
   if (total == 0) return LBM_OK;
-  int64_t nf_all = 0;
-  for (int d = 0; d < b->count; ++d) nf_all += nf[size_t(d)];
-  e = hipMalloc(&b->d_cells, size_t(total) * 4);
+  std::vector<unsigned long long> hmask(nchunks);
+  e = hipMemcpy(hmask.data(), b->d_lmask, nchunks * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bhip(b, e, "reading the list bitmap");
+  std::vector<uint32_t> hbase(nchunks);
+  uint32_t run = 0;
+  for (size_t k = 0; k < nchunks; ++k) {
+    hbase[k] = run;
+    run += uint32_t(__builtin_popcountll(hmask[k]));
+  }
+  if (int64_t(run) != nf_all) return bfail(b, LBM_ERR_DEVICE, "boundary list: bitmap and counts disagree");
+  std::vector<uint4> hpack(nchunks);
+  for (size_t k = 0; k < nchunks; ++k)
+    hpack[k] = make_uint4(uint32_t(hmask[k]), uint32_t(hmask[k] >> 32), hbase[k], 0u);
+  e = hipMemcpy(b->d_lbase, hbase.data(), nchunks * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&b->d_lpack, nchunks * sizeof(uint4));
+  if (e == hipSuccess) e = hipMemcpy(b->d_lpack, hpack.data(), nchunks * sizeof(uint4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&b->d_cells, size_t(total) * 4);
   if (e == hipSuccess) e = hipMalloc(&b->d_bits, size_t(total) * 4);
   if (e == hipSuccess) e = hipMalloc(&b->d_yz, size_t(std::max<int64_t>(nf_all, 1)) * 4);
+  if (e == hipSuccess) e = hipMalloc(&b->d_side, size_t(std::max<int64_t>(nf_all, 1)) * 40);
   if (e == hipSuccess) e = hipMalloc(&b->d_dom, size_t(total) * 2);
   if (e != hipSuccess) return bhip(b, e, "hipMalloc(boundary list)");
-  // all fluid entries first (domain by domain), then all solid entries
-  int64_t nf_total = 0;
-  for (int d = 0; d < b->count; ++d) nf_total += nf[size_t(d)];
+  // fluid entries in global cell order (so each domain's are contiguous), then solid entries
   std::vector<uint16_t> hdom(static_cast<size_t>(total));
-  int64_t fbase = 0, sbase = nf_total;
+  int64_t fbase = 0, sbase = nf_all;
   for (int d = 0; d < b->count && e == hipSuccess; ++d) {
     if (nf[size_t(d)] + ns[size_t(d)] == 0) continue;
     const Geometry g{b->dims[3 * d], b->dims[3 * d + 1], b->dims[3 * d + 2], 0};
     e = hipMemsetAsync(b->d_counters, 0, 4 * sizeof(uint32_t), b->stream);
     if (e == hipSuccess)
-      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->d_counters, b->d_cells + fbase, b->d_bits + fbase,
-                          b->d_yz + fbase, nf[size_t(d)], b->d_cells + sbase, b->d_bits + sbase, ns[size_t(d)],
+      e = launch_classify(b->d_mask + b->offs[size_t(d)], g, b->offs[size_t(d)], b->d_counters, b->d_lmask, b->d_lbase,
+                          b->d_cells, b->d_bits, b->d_yz, b->d_cells + sbase, b->d_bits + sbase, ns[size_t(d)],
                           b->stream);
     std::fill(hdom.begin() + fbase, hdom.begin() + fbase + nf[size_t(d)], uint16_t(d));
     std::fill(hdom.begin() + sbase, hdom.begin() + sbase + ns[size_t(d)], uint16_t(d));
@@ -377,10 +409,16 @@ int build_lists(lbm_batch* b) {
   if (e == hipSuccess) e = hipMemcpyAsync(b->d_dom, hdom.data(), hdom.size() * 2, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bhip(b, e, "boundary list (fill)");
+  b->solid_first.assign(size_t(b->count), 0);
+  b->solid_count.assign(size_t(b->count), 0);
+  int64_t sb = nf_all;
   for (int d = 0; d < b->count; ++d) {
-    b->n_fluid_b += nf[size_t(d)];
-    b->n_solid_b += ns[size_t(d)];
+    b->solid_first[size_t(d)] = sb;
+    b->solid_count[size_t(d)] = ns[size_t(d)];
+    sb += ns[size_t(d)];
   }
+  b->n_fluid_b = nf_all;
+  b->n_solid_b = total - nf_all;
   return LBM_OK;
 }
 
@@ -600,8 +638,8 @@ int lbm_batch_destroy(lbm_batch* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (int k = 0; k < 2; ++k)
     if (b->buf[k]) (void)hipFree(b->buf[k]);
-  void* ptrs[] = {b->d_mask, b->d_cells, b->d_bits, b->d_yz,   b->d_dom,
-                  b->d_counters, b->d_bad, b->d_step, b->d_doms, b->d_segs, b->d_wg_first};
+  void* ptrs[] = {b->d_mask,  b->d_cells, b->d_bits, b->d_yz,       b->d_dom,  b->d_lmask, b->d_lbase, b->d_lpack,
+                  b->d_side,  b->d_counters, b->d_bad, b->d_step, b->d_doms, b->d_segs,  b->d_wg_first};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -743,7 +781,18 @@ int lbm_batch_get_raw(lbm_batch* b, int d, void* out, size_t bytes, int on_devic
 }
 
 int lbm_batch_set_raw(lbm_batch* b, int d, const void* in, size_t bytes, int on_device) {
-  return raw_copy(b, d, const_cast<void*>(in), bytes, on_device, true);
+  const int r = raw_copy(b, d, const_cast<void*>(in), bytes, on_device, true);
+  if (r != LBM_OK) return r;
+  if (size_t(d) < b->solid_count.size() && b->solid_count[size_t(d)] > 0) {
+    // solid cells next to fluid hold the rest state at every step
+    BatchStepParams p = params(b, b->cur, 0);
+    for (int k = 0; k < 10; ++k) p.out[k] = const_cast<void*>(p.in[k]);
+    const int64_t f = b->solid_first[size_t(d)];
+    const hipError_t e = launch_batch_boundary(b->fmt, p, b->d_cells + f, nullptr, nullptr, b->d_dom + f, 0,
+                                               int(b->solid_count[size_t(d)]), b->stream);
+    if (e != hipSuccess) return bhip(b, e, "set_raw (solid cells)");
+  }
+  return LBM_OK;
 }
 
 int lbm_batch_step(lbm_batch* b, int n) {
@@ -835,7 +884,7 @@ int lbm_batch_memory_bytes(const lbm_batch* b, size_t* state_bytes, size_t* tota
   if (state_bytes) *state_bytes = s;
   if (total_bytes)
     *total_bytes = s + (b->d_mask ? size_t(b->N) : 0) + size_t(b->n_fluid_b + b->n_solid_b) * 10 +
-                   size_t(b->n_fluid_b) * 4 +
+                   size_t(b->n_fluid_b) * 44 + (b->d_lmask ? size_t((b->N + 63) / 64) * 28 : 0) +
                    b->plan.segs.size() * sizeof(BatchSeg) + b->plan.wg_first.size() * 4 +
                    size_t(b->count) * sizeof(BatchDomain) + 32;
   return LBM_OK;

@@ -1,21 +1,23 @@
 // lbm_boundary.hip -- the boundary pass over the compacted cell list, and the
 // list's construction.
 //
-// The fluid pass treats every cell alike (Sec. 4.2); this pass then visits
-// only the listed cells (lbm_boundary_cell.h holds the per-cell update).
+// The fluid pass treats every cell alike (Sec. 4.2) and keeps, for each listed
+// fluid cell, its unrounded result; this pass then visits only the listed
+// cells (lbm_boundary_cell.h holds the per-cell update).
 #include "lbm_boundary_cell.h"
 
 namespace lbm {
 
-// Listed fluid cells: 32 lanes each (8 cells per 256-thread block).
+// Listed fluid cells: one lane each; entry e is slot e of the side buffer.
 template <int FMT>
 __global__ void __launch_bounds__(256) boundary_fluid_kernel(StepParams a, const uint32_t* __restrict__ cells,
                                                              const uint32_t* __restrict__ bits,
-                                                             const uint32_t* __restrict__ yz, int count) {
+                                                             const uint32_t* __restrict__ yz,
+                                                             const uint32_t* __restrict__ order, int count) {
   const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
-  const int e = t >> 5;
-  if (e >= count) return;  // whole 32-lane groups leave together
-  boundary_group<FMT>(a, cells[e], bits[e], yz[e], t & 31);
+  if (t >= count) return;
+  const uint32_t e = order ? order[t] : uint32_t(t);
+  boundary_fix<FMT>(a, e, cells[e], bits[e], yz[e]);
 }
 
 // Listed solid cells: one lane each.
@@ -28,13 +30,13 @@ __global__ void __launch_bounds__(256) boundary_solid_kernel(StepParams a, const
 }
 
 hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
-                           const uint32_t* yz, int nfluid, int nsolid, hipStream_t s) {
+                           const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
   if (nfluid > 0) {
-    const dim3 grid(uint32_t((int64_t(nfluid) * 32 + 255) / 256));
+    const dim3 grid(uint32_t((nfluid + 255) / 256));
     if (fmt == FMT_F32)
-      hipLaunchKernelGGL(boundary_fluid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, nfluid);
+      hipLaunchKernelGGL(boundary_fluid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
     else
-      hipLaunchKernelGGL(boundary_fluid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, nfluid);
+      hipLaunchKernelGGL(boundary_fluid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -50,14 +52,15 @@ hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, 
 }
 
 // ------------------------------------------------------------ compaction ---
-// Classifies every cell; the listed ones are appended with one atomic per
-// wavefront and kind (ballot + popcount): fluid entries to cells_f / bits_f,
-// solid ones to cells_s / bits_s.  counters[0] counts fluid entries,
-// counters[1] solid ones, counters[2] and [3] are the two fill cursors.  Order
-// within each part is irrelevant: entries are independent.
-__global__ void __launch_bounds__(256) classify_kernel(const uint8_t* __restrict__ mask, Geometry g,
-                                                       uint32_t* counters, uint32_t* cells_f, uint32_t* bits_f,
-                                                       uint32_t* yz_f, uint32_t cap_f, uint32_t* cells_s,
+// Classifies every cell of a domain.  Listed fluid cells are kept in raster
+// order (their slot comes from the global bitmap and its prefix counts, so
+// the fluid pass can find a cell's slot without searching); listed solid
+// cells are appended with one atomic per wavefront (their order does not
+// matter).
+__global__ void __launch_bounds__(256) classify_kernel(const uint8_t* __restrict__ mask, Geometry g, uint32_t goff,
+                                                       uint32_t* counters, unsigned long long* lmask,
+                                                       const uint32_t* __restrict__ lbase, uint32_t* cells_f,
+                                                       uint32_t* bits_f, uint32_t* yz_f, uint32_t* cells_s,
                                                        uint32_t* bits_s, uint32_t cap_s) {
   const uint32_t N = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(g.nz);
   const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -103,50 +106,54 @@ __global__ void __launch_bounds__(256) classify_kernel(const uint8_t* __restrict
       listed = b != 0;
     }
   }
-  // wavefront compaction
-  const unsigned long long fvote = __ballot(listed && !solid);
+  const bool lfluid = listed && !solid;
+  const unsigned long long fvote = __ballot(lfluid);
   const unsigned long long svote = __ballot(listed && solid);
   if ((fvote | svote) == 0ull) return;
   const int lane = __lane_id();
-  const int leader = __ffsll(static_cast<long long>(fvote | svote)) - 1;
-  uint32_t fbase = 0, sbase = 0;
-  if (lane == leader) {
-    atomicAdd(&counters[0], uint32_t(__popcll(fvote)));
-    atomicAdd(&counters[1], uint32_t(__popcll(svote)));
-    if (cells_f != nullptr) {
-      fbase = atomicAdd(&counters[2], uint32_t(__popcll(fvote)));
-      sbase = atomicAdd(&counters[3], uint32_t(__popcll(svote)));
+  const uint32_t gcell = goff + cell;
+  if (lbase == nullptr) {
+    // count pass: counts, and the fluid cells into the global bitmap (a
+    // domain need not start on a 64-cell boundary, hence the atomic OR)
+    const int leader = __ffsll(static_cast<long long>(fvote | svote)) - 1;
+    if (lane == leader) {
+      atomicAdd(&counters[0], uint32_t(__popcll(fvote)));
+      atomicAdd(&counters[1], uint32_t(__popcll(svote)));
+    }
+    if (lfluid) atomicOr(&lmask[gcell >> 6], 1ull << (gcell & 63u));
+    return;
+  }
+  // fill pass
+  const unsigned long long below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+  const int sleader = svote ? __ffsll(static_cast<long long>(svote)) - 1 : -1;
+  uint32_t sbase = 0;
+  if (lane == sleader) sbase = atomicAdd(&counters[3], uint32_t(__popcll(svote)));
+  if (sleader >= 0) sbase = __shfl(sbase, sleader);
+  if (listed && solid) {
+    const uint32_t k = sbase + uint32_t(__popcll(svote & below));
+    if (k < cap_s) {
+      cells_s[k] = cell;
+      bits_s[k] = b;
     }
   }
-  if (cells_f == nullptr) return;
-  fbase = __shfl(fbase, leader);
-  sbase = __shfl(sbase, leader);
-  if (listed) {
-    const unsigned long long below = lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
-    if (solid) {
-      const uint32_t k = sbase + uint32_t(__popcll(svote & below));
-      if (k < cap_s) {
-        cells_s[k] = cell;
-        bits_s[k] = b;
-      }
-    } else {
-      const uint32_t k = fbase + uint32_t(__popcll(fvote & below));
-      if (k < cap_f) {
-        cells_f[k] = cell;
-        bits_f[k] = b;
-        yz_f[k] = yz;
-      }
-    }
+  if (lfluid) {
+    const unsigned long long w = lmask[gcell >> 6];
+    const uint32_t bit = gcell & 63u;
+    const unsigned long long wb = bit == 0 ? 0ull : (w & ((~0ull) >> (64u - bit)));
+    const uint32_t k = lbase[gcell >> 6] + uint32_t(__popcll(wb));
+    cells_f[k] = cell;
+    bits_f[k] = b;
+    yz_f[k] = yz;
   }
 }
 
-hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t* counters, uint32_t* cells_f,
-                           uint32_t* bits_f, uint32_t* yz_f, uint32_t cap_f, uint32_t* cells_s, uint32_t* bits_s,
-                           uint32_t cap_s, hipStream_t s) {
+hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t goff, uint32_t* counters,
+                           unsigned long long* lmask, const uint32_t* lbase, uint32_t* cells_f, uint32_t* bits_f,
+                           uint32_t* yz_f, uint32_t* cells_s, uint32_t* bits_s, uint32_t cap_s, hipStream_t s) {
   const uint64_t N = uint64_t(g.nx) * g.ny * g.nz;
   const dim3 block(256), grid(uint32_t((N + 255) / 256));
-  hipLaunchKernelGGL(classify_kernel, grid, block, 0, s, mask, g, counters, cells_f, bits_f, yz_f, cap_f, cells_s,
-                     bits_s, cap_s);
+  hipLaunchKernelGGL(classify_kernel, grid, block, 0, s, mask, g, goff, counters, lmask, lbase, cells_f, bits_f, yz_f,
+                     cells_s, bits_s, cap_s);
   return hipGetLastError();
 }
 

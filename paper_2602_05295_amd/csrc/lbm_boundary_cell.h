@@ -1,15 +1,18 @@
 // lbm_boundary_cell.h -- the boundary pass of one listed cell (device code
 // shared by the single-domain and the batched boundary kernels).
 //
-// A listed fluid cell is recomputed from scratch: each of its 27 incoming
-// distributions is the pull-streamed f+ of its source, except on links whose
-// source is solid (halfway bounce-back: f_i(x) = f+_opp(i)(x)), links entering
-// through the inflow face (the moment boundary of Sec. 3.2 with p on the face:
-// rho^p = rho^x, u^p = u_in and the post-collision non-equilibrium stress of
-// x) and links entering through the outflow face (zero gradient:
-// f+_i(nx-1, y - c_y, z - c_z)).  The new moments are encoded once and
-// overwrite what the fluid pass wrote, so each cell has one writer, no atomics
-// and a single rounding.  Solid cells next to fluid are reset to rest.
+// The rules are those of a listed fluid cell recomputed from scratch: each of
+// its 27 incoming distributions is the pull-streamed f+ of its source, except
+// on links whose source is solid (halfway bounce-back: f_i(x) = f+_opp(i)(x)),
+// links entering through the inflow face (the moment boundary of Sec. 3.2
+// with p on the face: rho^p = rho^x, u^p = u_in and the post-collision
+// non-equilibrium stress of x) and links entering through the outflow face
+// (zero gradient: f+_i(nx-1, y - c_y, z - c_z)).  Since the fluid pass already
+// pulled every other link, the pass starts from the fluid pass's unrounded
+// moments and replaces only the changed links.  The new moments are encoded
+// once and overwrite what the fluid pass wrote, so each cell has one writer,
+// no atomics and a single rounding.  Solid cells next to fluid are reset to
+// rest.
 #pragma once
 
 #include "lbm_device.h"
@@ -110,88 +113,119 @@ __device__ inline void rest_words(uint32_t w[5]) {
   w[4] = qn | (qn << 16);
 }
 
-// The distribution that listed fluid cell `cell` (coordinates x, y, z; flags
-// b) receives on link i = (cx + 1) + 3 (cy + 1) + 9 (cz + 1) under the
-// boundary rules: one source cell, its post-collision coefficients (with the
-// inflow velocity on inflow links), evaluated in the link's direction (the
-// opposite one on bounce-back links).
+// Post-collision coefficients of cell q (with the inflow velocity when
+// `inflow`: rho^p = rho^q, u^p = u_in, the non-equilibrium stress of q).
 template <int FMT>
-__device__ inline float boundary_link(const StepParams& a, uint32_t cell, uint32_t b, int x, int y, int z, int i) {
-  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-  uint32_t q = cell;
-  bool flip = false, inflow = false;
-  if ((b & BIT_INFLOW) && cx == 1) {
-    inflow = true;
-  } else if ((b & BIT_OUTFLOW) && cx == -1) {
-    q = uint32_t(nx - 1) + uint32_t(nx) * (uint32_t(wrap_step(y, -cy, ny)) + uint32_t(ny) * uint32_t(wrap_step(z, -cz, nz)));
-  } else if ((b >> i) & 1u) {
-    flip = true;
-  } else {
-    q = uint32_t(wrap_step(x, -cx, nx)) +
-        uint32_t(nx) * (uint32_t(wrap_step(y, -cy, ny)) + uint32_t(ny) * uint32_t(wrap_step(z, -cz, nz)));
-  }
+__device__ inline void source_coeffs(const StepParams& a, uint32_t q, bool inflow, float A[NA]) {
   const CellIn c = load_cell_b<FMT>(a, q);
   float Nn[6];
   collide_neq(c.N, a.om1, Nn);
-  float A[NA];
   if (inflow) {
     const float jin[3] = {c.rho * a.u_in[0], c.rho * a.u_in[1], c.rho * a.u_in[2]};
     hermite_coeffs(c.dr, jin, a.u_in, Nn, A);
   } else {
     hermite_coeffs(c.dr, c.j, c.u, Nn, A);
   }
-  return flip ? eval_link(A, -cx, -cy, -cz) : eval_link(A, cx, cy, cz);
 }
 
-// Sum over the 32 lanes of a half-wavefront, complete in its last lane (31 or
-// 63): an inclusive scan inside each row of 16 lanes (DPP row shifts 1, 2, 4,
-// 8, reading 0 past the row start), then the total of row 0 (2) added into
-// row 1 (3) with a row broadcast of lane 15.
-__device__ inline float half_wave_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));  // row_shr:1
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));  // row_shr:2
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));  // row_shr:4
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));  // row_shr:8
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15
-  return v;
+// dm += (moments of link c) * df
+__device__ inline void add_link(float m[10], int cx, int cy, int cz, float df) {
+  const float fx = float(cx), fy = float(cy), fz = float(cz);
+  m[0] += df;
+  m[1] = fmaf(fx, df, m[1]);
+  m[2] = fmaf(fy, df, m[2]);
+  m[3] = fmaf(fz, df, m[3]);
+  m[4] = fmaf(fx * fx - R3, df, m[4]);
+  m[5] = fmaf(fy * fy - R3, df, m[5]);
+  m[6] = fmaf(fz * fz - R3, df, m[6]);
+  m[7] = fmaf(fx * fy, df, m[7]);
+  m[8] = fmaf(fx * fz, df, m[8]);
+  m[9] = fmaf(fy * fz, df, m[9]);
 }
 
-// One listed fluid cell per 32-lane group, link i on lane i (lanes 27..31
-// add nothing): each lane takes its link's distribution and its share of the
-// ten moments, the group sums them, and its last lane writes the cell once.
-// All lanes of a group must be active (the caller keeps groups whole) and a
-// group must be one half of a wavefront.
-// yz: the cell's y | z << 16 (stored with the list, so no division is needed).
+// Post-collision coefficients of the rest state as stored: FP32 rest is
+// exactly zero; the 16-bit rest codes decode to a fixed state near rest.
+// Every solid cell a fluid cell reads is listed, and listed solid cells hold
+// these codes at the start of every step (the boundary pass writes them, and
+// every way of setting the state keeps them), so the distribution the fluid
+// pass pulled from a solid neighbour is a constant of its direction.
 template <int FMT>
-__device__ inline void boundary_group(const StepParams& a, uint32_t cell, uint32_t b, uint32_t yz, int i) {
-  const int nx = a.g.nx, ny = a.g.ny;
+__device__ inline void rest_coeffs(float om1, float A[NA]) {
+  if constexpr (FMT == FMT_F32) {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) A[k] = 0.0f;
+  } else {
+    uint32_t w[5];
+    rest_words(w);
+    const CellIn c = cell_from_words(w);
+    float Nn[6];
+    collide_neq(c.N, om1, Nn);
+    hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+  }
+}
+
+// Listed fluid cell `cell` (list entry / side slot e, flags b, yz = y | z << 16).
+// The fluid pass pulled every link periodically and left its unrounded
+// moments in the side buffer; only the links the boundary rules change are
+// corrected here (new minus pulled distribution of each such link), and the
+// cell is written once:
+//   - bounce-back link i (source solid): new f+_opp(i)(x); pulled: f+_i of
+//     the stored rest state (rest_coeffs), no load;
+//   - inflow link (cx = 1 on the inflow face): new f+_i with the inflow
+//     coefficients of x, pulled f+_i of the periodic image (nx-1, y-cy, z-cz);
+//   - outflow link (cx = -1 on the outflow face): new f+_i of (nx-1, y-cy,
+//     z-cz), pulled f+_i of the periodic image (0, y-cy, z-cz).
+// Bounce-back links are walked per lane (a bit scan); face links, the same
+// nine for every face cell, in lockstep so that neighbouring face cells'
+// loads coalesce.
+template <int FMT>
+__device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t cell, uint32_t b, uint32_t yz) {
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int y = int(yz & 0xFFFFu), z = int(yz >> 16);
   const int x = int(cell - uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z)));
   float m[10];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) m[k] = 0.0f;
-  if (i < 27) {
-    const float f = boundary_link<FMT>(a, cell, b, x, y, z, i);
-    const float fx = float(i % 3 - 1), fy = float((i / 3) % 3 - 1), fz = float(i / 9 - 1);
-    m[0] = f;
-    m[1] = fx * f;
-    m[2] = fy * f;
-    m[3] = fz * f;
-    m[4] = (fx * fx - R3) * f;
-    m[5] = (fy * fy - R3) * f;
-    m[6] = (fz * fz - R3) * f;
-    m[7] = fx * fy * f;
-    m[8] = fx * fz * f;
-    m[9] = fy * fz * f;
+  for (int k = 0; k < 10; ++k) m[k] = a.lc.side[size_t(k) * a.lc.nside + e];
+  float Aown[NA];
+  source_coeffs<FMT>(a, cell, false, Aown);
+  uint32_t bb = b & 0x7FFFFFFu & ~(1u << 13);
+  if (bb) {
+    float Arest[NA];
+    rest_coeffs<FMT>(a.om1, Arest);
+    while (bb) {
+      const int i = __ffs(bb) - 1;
+      bb &= bb - 1u;
+      const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+      add_link(m, cx, cy, cz, eval_link(Aown, -cx, -cy, -cz) - eval_link(Arest, cx, cy, cz));
+    }
   }
-#pragma unroll
-  for (int k = 0; k < 10; ++k) m[k] = half_wave_sum(m[k]);
-  if (i == 31) {
-    const float j[3] = {m[1], m[2], m[3]};
-    const float P[6] = {m[4], m[5], m[6], m[7], m[8], m[9]};
-    store_cell_b<FMT>(a, cell, m[0], j, P);
+  if (b & (BIT_INFLOW | BIT_OUTFLOW)) {
+    const bool in = (b & BIT_INFLOW) != 0;
+    const int cx = in ? 1 : -1;
+    float Ain[NA];
+    if (in) source_coeffs<FMT>(a, cell, true, Ain);
+    const uint32_t ximg = in ? uint32_t(nx - 1) : 0u;  // the periodic image the fluid pass pulled from
+    for (int cz = -1; cz <= 1; ++cz) {
+      for (int cy = -1; cy <= 1; ++cy) {
+        const uint32_t yzo =
+            uint32_t(nx) * (uint32_t(wrap_step(y, -cy, ny)) + uint32_t(ny) * uint32_t(wrap_step(z, -cz, nz)));
+        float As[NA];
+        source_coeffs<FMT>(a, ximg + yzo, false, As);
+        const float fold = eval_link(As, cx, cy, cz);
+        float fnew;
+        if (in) {
+          fnew = eval_link(Ain, cx, cy, cz);
+        } else {  // zero gradient: the face cell (nx - 1, y - cy, z - cz)
+          source_coeffs<FMT>(a, uint32_t(nx - 1) + yzo, false, As);
+          fnew = eval_link(As, cx, cy, cz);
+        }
+        add_link(m, cx, cy, cz, fnew - fold);
+      }
+    }
   }
+  const float j[3] = {m[1], m[2], m[3]};
+  const float P[6] = {m[4], m[5], m[6], m[7], m[8], m[9]};
+  store_cell_b<FMT>(a, cell, m[0], j, P);
 }
 
 // A listed solid cell: reset to rest.

@@ -18,6 +18,16 @@ struct Geometry {
   int inflow;
 };
 
+// Listed fluid cells, in raster order: for each 64-cell word c >> 6,
+// lpack holds {bits 0..31, bits 32..63, prefix count, 0}; bit (c & 63) marks
+// cell c, and its slot (position in the list) is the prefix count plus the
+// marked cells before it in that word.  One 16-byte load gives both.
+struct ListedCells {
+  const uint4* lpack;
+  float* side;      // 10 planes of nside floats: the fluid pass's unrounded moments of each listed cell
+  uint32_t nside;
+};
+
 struct StepParams {
   const void* in[10];  // state planes read (FP32: 10 float planes, Q16: 5 word planes)
   void* out[10];       // state planes written
@@ -26,7 +36,17 @@ struct StepParams {
   uint32_t key;        // dither key of this step
   int dither;          // 0: round to nearest; else add the dither of `key`
   float u_in[3];
+  ListedCells lc;      // lc.side == nullptr: no listed cells
 };
+
+// Slot of cell c given its packed word w, or -1 if c is not listed.
+__device__ inline int listed_slot_in(const uint4& w, uint32_t c) {
+  const uint32_t bit = c & 63u;
+  const unsigned long long m = (static_cast<unsigned long long>(w.y) << 32) | w.x;
+  if (((m >> bit) & 1ull) == 0ull) return -1;
+  const unsigned long long below = bit == 0 ? 0ull : (m & ((~0ull) >> (64u - bit)));
+  return int(w.z + uint32_t(__popcll(below)));
+}
 
 // Adjoint of one FP32 step: lam_out = J(m)^T lam_in.
 struct AdjParams {
@@ -61,16 +81,22 @@ extern const int kFluidTileRows[4];
 FluidPlan fluid_plan(const Geometry& g, int rows, int cus);
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s);
 
-// Boundary pass over the compacted list: nfluid fluid entries (with their
-// y | z << 16 in yz), then nsolid solid entries (cells + nfluid).
+// Boundary pass: the nfluid listed fluid cells (list order = slot order,
+// with their y | z << 16 in yz) take the fluid pass's moments from p.lc.side
+// and the corrections of their boundary links; then the nsolid listed solid
+// cells (cells + nfluid) are reset to rest.
+// order (may be null): the order in which the fluid entries are visited.
 hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
-                           const uint32_t* yz, int nfluid, int nsolid, hipStream_t s);
+                           const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s);
 
-// Boundary list: count pass (cells_f == nullptr) or fill pass (fluid entries
-// to cells_f / bits_f / yz_f, solid entries to cells_s / bits_s).
-hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t* counters, uint32_t* cells_f,
-                           uint32_t* bits_f, uint32_t* yz_f, uint32_t cap_f, uint32_t* cells_s, uint32_t* bits_s,
-                           uint32_t cap_s, hipStream_t s);
+// Boundary list of one domain whose cells start at global index goff.
+// Count pass (lbase == nullptr): counters[0] / [1] receive the fluid / solid
+// counts and the fluid cells are OR-ed into lmask (indexed by global cell).
+// Fill pass: fluid entries go to their slots (cells_f / bits_f / yz_f are the
+// whole list), solid entries to cells_s / bits_s via the cursor counters[3].
+hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t goff, uint32_t* counters,
+                           unsigned long long* lmask, const uint32_t* lbase, uint32_t* cells_f, uint32_t* bits_f,
+                           uint32_t* yz_f, uint32_t* cells_s, uint32_t* bits_s, uint32_t cap_s, hipStream_t s);
 
 // Codec / initialisation / read-back.
 hipError_t launch_set_moments(int fmt, const float* m, void* const out[10], const uint8_t* mask, int64_t N,

@@ -349,3 +349,34 @@ def test_health_check_flags_nan_and_saturation(H):
     with H.HomeLBM(dims, 0.6, fmt="q16") as s:
         s.set_moments(m)
         assert s.check() > 0
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_set_raw_puts_listed_solid_cells_back_at_rest(H, fmt):
+    """The boundary pass relies on solid cells next to fluid holding the rest
+    state; a raw state with anything else there must give the same step."""
+    dims = (26, 19, 14)
+    _note("set_raw solid rest", fmt)
+    mask = W.sphere_mask(*dims, phi=0.1, rmin=1.5, rmax=3.5, seed=9)
+    m = W.random_moments(*dims, seed=12, dj=0.02, dp=0.003).astype(np.float32)
+    with H.HomeLBM(dims, 0.6, mask=mask, fmt=fmt) as s:
+        s.set_options(dither_mode=1, seed=5)
+        s.set_moments(m)
+        raw = s.get_raw().copy()
+        s.step(2)
+        ref = s.get_raw().copy()
+    bad = raw.copy()
+    rng = np.random.default_rng(1)
+    noise = rng.integers(0, 2**32, size=bad.shape, dtype=np.uint64).astype(np.uint32)
+    if fmt == "fp32":
+        bad[:, mask == 1] = rng.standard_normal((10, int(mask.sum()))).astype(np.float32)
+    else:
+        bad[:, mask == 1] = noise[:, mask == 1]
+    with H.HomeLBM(dims, 0.6, mask=mask, fmt=fmt) as s:
+        s.set_options(dither_mode=1, seed=5)
+        s.set_raw(bad)
+        s.step(2)
+        got = s.get_raw()
+    fl = mask == 0
+    assert np.array_equal(got[:, fl], ref[:, fl])
+
