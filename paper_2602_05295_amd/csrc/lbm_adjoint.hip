@@ -6,9 +6,9 @@
 // lam(t) = A'(m)^T S^T lam(t+1): the transposed 1D passes (adjoint of the
 // projection, the shift reversed, adjoint of the reconstruction) followed by
 // the per-cell transpose of A' (lbm_device.h, coeffs_T).  The boundary pass
-// overwrote the listed cells, so the fluid adjoint reads lam(t+1) as zero
-// there and at solid cells; the boundary adjoint then gathers, for every cell
-// a listed cell reads, the adjoint of what was read (adjoint_gather_kernel).
+// overwrote the listed solid cells with rest, so the fluid adjoint reads lam(t+1) as zero
+// there; the boundary pass's corrections of changed links are then added by
+// two small kernels (adjoint_bounce_kernel, adjoint_face_kernel).
 //
 // The fluid adjoint uses the forward pass's tiling and work split (64-wide
 // tiles of 8 or 13 rows, phase-aligned z segments): y pass first (the halo
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) adjoint_fluid_kernel(AdjParams
         load10(a.lam_in, c1, gn);
         fn = a.flags[c1];
       }
-      if (fl != 0) {
+      if (fl == 2) {  // a solid cell's new moments are overwritten with rest: no dependence
 #pragma unroll
         for (int k = 0; k < 10; ++k) g[k] = 0.0f;
       }
@@ -303,78 +303,79 @@ __device__ inline float link_dot(const float g[10], int cx, int cy, int cz) {
   return gf;
 }
 
-// Boundary adjoint as a gather, one thread per source cell s (a fluid cell
-// that some listed fluid cell reads, or a listed fluid cell itself).  s
-// collects, from every listed fluid cell t it feeds, the adjoint of the
-// distribution t took from it:
-//   - regular pulls: t = s + c_i reads f+_i(s);
-//   - outflow (zero gradient): s on the outflow face feeds the face cell
-//     t = s + (0, c_y, c_z) on link (-1, c_y, c_z);
-//   - s's own links when s is listed: bounce-back links read f+_opp(i)(s);
-//     inflow links read the inflow coefficients of s (their own Jacobian).
-// Link types follow from the flags and the faces alone, so no per-link data
-// is stored.  The sum goes through one transposed Jacobian of s and is added
-// to what the fluid adjoint wrote for s (one writer per cell, no atomics).
-__global__ void __launch_bounds__(256) adjoint_gather_kernel(AdjParams a, const uint32_t* __restrict__ src, int count) {
+// The boundary pass takes a listed fluid cell's fluid-pass result and adds,
+// per changed link, (new - pulled) distribution.  The fluid adjoint already
+// carries the pulled part (it is the fluid pass's own dependence, the solid
+// sources' share being discarded at those cells).  What remains:
+//   - bounce-back link i of x: + f+_opp(i)(x), through x's own coefficients;
+//     the pulled rest state is a constant;
+//   - inflow link of x (cx = 1): + f+_i with x's inflow coefficients, - f+_i of
+//     the periodic image (nx-1, y-cy, z-cz);
+//   - outflow link of x (cx = -1): + f+_i of the face cell (nx-1, y-cy, z-cz),
+//     - f+_i of the periodic image (0, y-cy, z-cz).
+// The first is added by adjoint_bounce_kernel (one lane per listed fluid
+// cell, its own data only); the face terms by adjoint_face_kernel, a gather
+// over the two x-face planes.  Both add to what the fluid adjoint wrote (one
+// writer per cell in each kernel, no atomics).
+__global__ void __launch_bounds__(256) adjoint_bounce_kernel(AdjParams a, const uint32_t* __restrict__ cells,
+                                                             const uint32_t* __restrict__ bits, int count) {
   const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= count) return;
+  uint32_t bb = bits[e] & 0x7FFFFFFu & ~(1u << 13);
+  if (bb == 0u) return;
+  const uint32_t x = cells[e];
+  float g[10];
+  load10(a.lam_in, x, g);
+  float gA[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) gA[k] = 0.0f;
+  while (bb) {
+    const int i = __ffs(bb) - 1;
+    bb &= bb - 1u;
+    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    add_basis(link_dot(g, cx, cy, cz), -cx, -cy, -cz, gA);
+  }
+  float m[10];
+  load10(a.m, x, m);
+  float out[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) out[k] = 0.0f;
+  const CellLin cl = cell_lin(m, a.om1, nullptr);
+  coeffs_T(cl, a.om1, gA, true, out);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) a.lam_out[k][x] += out[k];
+}
+
+// One thread per cell of the two x-face planes (inflow on: x = 0 inflow,
+// x = nx - 1 outflow).  s at x = nx - 1 is the periodic image of the inflow
+// cells (0, y+cy, z+cz) (-) and the zero-gradient source of the outflow cells
+// (nx-1, y+cy, z+cz) (+); s at x = 0 is the periodic image of the outflow
+// cells (nx-1, y+cy, z+cz) (-) and takes its own inflow links (+, through its
+// inflow coefficients).  Every face cell is listed (faces hold no solids).
+__global__ void __launch_bounds__(256) adjoint_face_kernel(AdjParams a) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const bool open_x = a.g.inflow != 0;
-  const uint32_t s = src[e];
-  const int x = int(s % uint32_t(nx));
-  const int y = int((s / uint32_t(nx)) % uint32_t(ny));
-  const int z = int(s / (uint32_t(nx) * uint32_t(ny)));
-  const bool listed = a.flags[s] == 1;
-  const bool in_face = open_x && x == 0;
-  const bool out_face = open_x && x == nx - 1;
-  float gown[10];
-  if (listed) load10(a.lam_in, s, gown);
+  const int t = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= 2 * ny * nz) return;
+  const bool out_face = t >= ny * nz;
+  const int yz = out_face ? t - ny * nz : t;
+  const int y = yz % ny, z = yz / ny;
+  const int x = out_face ? nx - 1 : 0;
+  const uint32_t s = uint32_t(x) + uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z));
   float gA[NA], gin[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) gA[k] = gin[k] = 0.0f;
-  bool any_in = false;
-  for (int i = 0; i < 27; ++i) {
-    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-    const uint32_t yz_up = uint32_t(nx) * (uint32_t(wrapi(y + cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z + cz, nz)));
-    // regular pull by t = s + c
-    int tx = x + cx;
-    bool valid = true;
-    if (open_x)
-      valid = tx >= 0 && tx < nx;
-    else
-      tx = wrapi(tx, nx);
-    if (valid) {
-      const uint32_t t = uint32_t(tx) + yz_up;
-      if (a.flags[t] == 1) {
-        float g[10];
-        load10(a.lam_in, t, g);
-        add_basis(link_dot(g, cx, cy, cz), cx, cy, cz, gA);
-      }
-    }
-    // zero-gradient outflow: t = s + (0, c_y, c_z) on the face reads s on link (-1, c_y, c_z)
-    if (out_face && cx == -1) {
-      const uint32_t t = uint32_t(x) + yz_up;
+  for (int cz = -1; cz <= 1; ++cz) {
+    for (int cy = -1; cy <= 1; ++cy) {
+      const uint32_t yzn = uint32_t(nx) * (uint32_t(wrapi(y + cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z + cz, nz)));
       float g[10];
-      load10(a.lam_in, t, g);
-      add_basis(link_dot(g, cx, cy, cz), cx, cy, cz, gA);
-    }
-    // own links of a listed cell
-    if (listed) {
-      if (in_face && cx == 1) {
-        add_basis(link_dot(gown, cx, cy, cz), cx, cy, cz, gin);
-        any_in = true;
-      } else if (!(out_face && cx == -1)) {
-        int sx = x - cx;
-        bool inside = true;
-        if (open_x)
-          inside = sx >= 0 && sx < nx;
-        else
-          sx = wrapi(sx, nx);
-        if (inside) {
-          const uint32_t q =
-              uint32_t(sx) + uint32_t(nx) * (uint32_t(wrapi(y - cy, ny)) + uint32_t(ny) * uint32_t(wrapi(z - cz, nz)));
-          if (a.flags[q] == 2) add_basis(link_dot(gown, cx, cy, cz), -cx, -cy, -cz, gA);  // bounce-back
-        }
+      if (out_face) {
+        load10(a.lam_in, yzn, g);  // inflow cell (0, y+cy, z+cz): s is its image on link (1, cy, cz)
+        add_basis(-link_dot(g, 1, cy, cz), 1, cy, cz, gA);
+        load10(a.lam_in, uint32_t(nx - 1) + yzn, g);  // outflow cell reading s on link (-1, cy, cz)
+        add_basis(link_dot(g, -1, cy, cz), -1, cy, cz, gA);
+      } else {
+        load10(a.lam_in, uint32_t(nx - 1) + yzn, g);  // outflow cell: s is its image on link (-1, cy, cz)
+        add_basis(-link_dot(g, -1, cy, cz), -1, cy, cz, gA);
       }
     }
   }
@@ -387,53 +388,16 @@ __global__ void __launch_bounds__(256) adjoint_gather_kernel(AdjParams a, const 
     const CellLin cl = cell_lin(m, a.om1, nullptr);
     coeffs_T(cl, a.om1, gA, true, out);
   }
-  if (any_in) {
+  if (!out_face) {  // own inflow links
+    float g[10];
+    load10(a.lam_in, s, g);
+    for (int cz = -1; cz <= 1; ++cz)
+      for (int cy = -1; cy <= 1; ++cy) add_basis(link_dot(g, 1, cy, cz), 1, cy, cz, gin);
     const CellLin cl = cell_lin(m, a.om1, a.u_in);
     coeffs_T(cl, a.om1, gin, false, out);
   }
 #pragma unroll
   for (int k = 0; k < 10; ++k) a.lam_out[k][s] += out[k];
-}
-
-// Source cells of the gather: fluid cells that are listed or feed a listed
-// fluid cell (by a regular pull or the outflow rule).  Compacted with one
-// atomic per wavefront; counter[0] receives the count.
-__global__ void __launch_bounds__(256) adjoint_sources_kernel(const uint8_t* __restrict__ flags, Geometry g,
-                                                              uint32_t* counter, uint32_t* list, uint32_t capacity) {
-  const uint32_t N = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(g.nz);
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  bool keep = false;
-  if (s < N && flags[s] != 2) {
-    keep = flags[s] == 1;
-    const int x = int(s % uint32_t(g.nx));
-    const int y = int((s / uint32_t(g.nx)) % uint32_t(g.ny));
-    const int z = int(s / (uint32_t(g.nx) * uint32_t(g.ny)));
-    for (int i = 0; i < 27 && !keep; ++i) {
-      const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-      int tx = x + cx;
-      if (g.inflow) {
-        if (tx < 0 || tx >= g.nx) continue;
-      } else {
-        tx = wrapi(tx, g.nx);
-      }
-      const uint32_t t =
-          uint32_t(tx) + uint32_t(g.nx) * (uint32_t(wrapi(y + cy, g.ny)) + uint32_t(g.ny) * uint32_t(wrapi(z + cz, g.nz)));
-      keep = flags[t] == 1;
-    }
-  }
-  const unsigned long long vote = __ballot(keep);
-  if (vote == 0ull) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll(static_cast<long long>(vote)) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, uint32_t(__popcll(vote)));
-  if (list == nullptr) return;
-  base = __shfl(base, leader);
-  if (keep) {
-    const unsigned long long below = lane == 0 ? 0ull : (vote & ((~0ull) >> (64 - lane)));
-    const uint32_t k = base + uint32_t(__popcll(below));
-    if (k < capacity) list[k] = s;
-  }
 }
 
 // flags: 1 = listed fluid cell, 2 = solid cell, 0 = other fluid cell
@@ -488,7 +452,8 @@ int cus() {
 }
 }  // namespace
 
-hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* src, int nsrc, hipStream_t s) {
+hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* cells, const uint32_t* bits, int nfluid,
+                          hipStream_t s) {
   // the forward pass's split at one of the two compiled tile heights (8 unless
   // 13 is asked for: the 13-row tile needs more registers than fit)
   const FluidPlan c = fluid_plan(p.g, rows == 13 ? 13 : 8, cus());
@@ -499,17 +464,18 @@ hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* src, int
     hipLaunchKernelGGL(adjoint_fluid_kernel<13>, dim3(uint32_t(c.nwg)), dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                        c.nwg);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nsrc <= 0) return e;
-  hipLaunchKernelGGL(adjoint_gather_kernel, dim3((nsrc + 255) / 256), dim3(256), 0, s, p, src, nsrc);
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_sources(const uint8_t* flags, const Geometry& g, uint32_t* counter, uint32_t* list,
-                                  uint32_t capacity, hipStream_t s) {
-  const uint64_t N = uint64_t(g.nx) * g.ny * g.nz;
-  hipLaunchKernelGGL(adjoint_sources_kernel, dim3(uint32_t((N + 255) / 256)), dim3(256), 0, s, flags, g, counter,
-                     list, capacity);
-  return hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nfluid > 0) {
+    hipLaunchKernelGGL(adjoint_bounce_kernel, dim3((nfluid + 255) / 256), dim3(256), 0, s, p, cells, bits, nfluid);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (p.g.inflow) {
+    const int n = 2 * p.g.ny * p.g.nz;
+    hipLaunchKernelGGL(adjoint_face_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_adjoint_flags(const uint8_t* mask, int64_t N, const uint32_t* cells, const uint32_t* bits,

@@ -39,8 +39,6 @@ struct lbm_ctx {
   uint32_t* d_counters = nullptr;     // 3 list counters
   unsigned long long* d_bad = nullptr;
   uint8_t* d_flags = nullptr;         // adjoint cell flags (built on first use)
-  uint32_t* d_src = nullptr;          // adjoint boundary gather: source cells
-  int64_t n_src = 0;
   bool flags_valid = false;
   bool list_built = false;
   int list_inflow = -1;
@@ -92,9 +90,6 @@ void free_list(lbm_ctx* c) {
   c->n_fluid_b = c->n_solid_b = 0;
   c->list_built = false;
   c->flags_valid = false;
-  if (c->d_src) (void)hipFree(c->d_src);
-  c->d_src = nullptr;
-  c->n_src = 0;
 }
 
 // Builds the boundary list on the device: count pass (counts and the bitmap
@@ -580,26 +575,10 @@ int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float*
   hipError_t e = hipSuccess;
   const int count = int(c->n_fluid_b + c->n_solid_b);
   if (!c->flags_valid) {
-    // cell flags, then the source cells of the boundary gather (count, allocate, fill)
+    // cell flags: 1 listed fluid, 2 solid
     if (!c->d_flags) e = hipMalloc(&c->d_flags, size_t(c->N));
     if (e == hipSuccess) e = launch_adjoint_flags(c->d_mask, c->N, c->d_cells, c->d_bits, count, c->d_flags, c->stream);
-    if (c->d_src) (void)hipFree(c->d_src);
-    c->d_src = nullptr;
-    c->n_src = 0;
-    uint32_t n = 0;
-    if (e == hipSuccess && count > 0) {
-      e = hipMemsetAsync(c->d_counters, 0, sizeof(uint32_t), c->stream);
-      if (e == hipSuccess) e = launch_adjoint_sources(c->d_flags, geom(c), c->d_counters, nullptr, 0, c->stream);
-      if (e == hipSuccess) e = hipMemcpyAsync(&n, c->d_counters, sizeof(n), hipMemcpyDeviceToHost, c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      if (e == hipSuccess && n > 0) {
-        e = hipMalloc(&c->d_src, size_t(n) * 4);
-        if (e == hipSuccess) e = hipMemsetAsync(c->d_counters, 0, sizeof(uint32_t), c->stream);
-        if (e == hipSuccess) e = launch_adjoint_sources(c->d_flags, geom(c), c->d_counters, c->d_src, n, c->stream);
-      }
-    }
     if (e != hipSuccess) return hip_fail(c, e, "adjoint flags");
-    c->n_src = n;
     c->flags_valid = true;
   }
   AdjParams p{};
@@ -613,7 +592,7 @@ int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float*
   p.g = geom(c);
   p.om1 = float(1.0 - 1.0 / c->tau);
   for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
-  e = launch_adjoint(p, c->opt.tile_rows, c->d_src, int(c->n_src), c->stream);
+  e = launch_adjoint(p, c->opt.tile_rows, c->d_cells, c->d_bits, int(c->n_fluid_b), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
   return LBM_OK;
 }

@@ -58,12 +58,11 @@ struct AdjParams {
   float om1;
   float u_in[3];
 };
-// Fluid adjoint (tile height `rows`: 8, 13, or 0 to choose), then the boundary
-// gather over the nsrc source cells in src.
-hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* src, int nsrc, hipStream_t s);
-// Source cells of the boundary gather (count pass with list == nullptr).
-hipError_t launch_adjoint_sources(const uint8_t* flags, const Geometry& g, uint32_t* counter, uint32_t* list,
-                                  uint32_t capacity, hipStream_t s);
+// Fluid adjoint (tile height `rows`: 8, 13, or 0 to choose), then the
+// boundary pass's changed links: bounce-back over the nfluid listed fluid
+// entries (cells / bits), face links over the two x-face planes.
+hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* cells, const uint32_t* bits, int nfluid,
+                          hipStream_t s);
 hipError_t launch_adjoint_flags(const uint8_t* mask, int64_t N, const uint32_t* cells, const uint32_t* bits,
                                 int count, uint8_t* flags, hipStream_t s);
 hipError_t launch_equilibrium_vjp(const float* rho, const float* u, const float* lam, const uint8_t* mask, int64_t N,
