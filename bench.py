@@ -245,6 +245,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--formats", default="q16,fp32", help="storage formats to run (the headline value is q16)")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint ratio and the channel run")
+    ap.add_argument("--only", choices=["adjoint", "channel", "batched"], default=None,
+                    help="run only this extra workload and print its JSON object (for profiling)")
+    ap.add_argument("--extra-steps", type=int, default=None, help="steps of the --only workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the reference kernel that "
                          "scales hardware byte counters)")
@@ -266,6 +269,11 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: 3 copies of {nbytes} bytes", file=sys.stderr, flush=True)
         del src, dst
+    if args.only is not None:
+        fn = {"adjoint": adjoint_ratio, "channel": channel, "batched": batched}[args.only]
+        kw = {} if args.extra_steps is None else {"steps": args.extra_steps}
+        print(json.dumps(fn(**kw)), flush=True)
+        return
     print(f"[bench] device {torch.cuda.get_device_name(0)}; building the {N}^3 field", file=sys.stderr, flush=True)
     rho, u = workload()
     rho_d = torch.from_numpy(rho).cuda()
