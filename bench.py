@@ -13,8 +13,11 @@ two device synchronisations with events on the stream the kernels run on.
 Prints one JSON line: MLUPS (whole job), the roofline of the dominant kernel
 (the fluid pass: algorithmic bytes per launch / mean launch time from HIP
 events, against the 8 TB/s HBM peak; measured HBM traffic from rocprofv3
-counters when a summary for the current kernel source is committed), and the
-CPU oracle timed on the host on a bounded sample of the same workload.
+counters when a summary for the current kernel source is committed), its
+VALU-issue roofline (measured wave instructions per launch / launch time,
+against 614.4 G/s; the 16-bit pass is bound by it), the adjoint/forward
+ratio, the obstacle channel and the 128-domain batch, and the CPU oracle timed
+on the host on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -37,6 +40,8 @@ TAU = 0.51
 BYTES_PER_CELL = {"q16": 40, "fp32": 80}   # one state read + one state written
 KERNEL_SOURCES = ["paper_2602_05295_amd/csrc/lbm_fluid.hip", "paper_2602_05295_amd/csrc/lbm_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fluid_256cubed_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "fluid_256cubed_valu.json")
+VALU_PEAK_G = 256 * 4 * 2.4 / 4  # G wave64 VALU instructions per second
 
 
 def kernel_hash() -> str:
@@ -45,6 +50,31 @@ def kernel_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _hash_checked(path: str, fmt: str, key: str):
+    """The committed counter summary's `key` for `fmt`, or None when the file
+    is missing or was taken on a different kernel source."""
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or fmt not in t.get("formats", {}):
+        return None
+    return t["formats"][fmt][key]
+
+
+def valu_roofline(fmt: str, kernel_ms: float):
+    """VALU-issue roofline of the fluid pass: measured wave instructions per
+    launch (rocprofv3 SQ_INSTS_VALU) / mean launch time, against 256 CUs x 4
+    SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction (packed FP32 off)."""
+    n = _hash_checked(VALU_FILE, fmt, "valu_instructions_per_launch")
+    if n is None:
+        return None
+    achieved = n / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": VALU_PEAK_G, "unit": "G wave-instructions/s",
+            "frac": round(achieved / VALU_PEAK_G, 4), "instructions_per_launch": n}
 
 
 def measured_traffic(fmt: str):
@@ -301,6 +331,7 @@ def main():
         return
     q = res["q16"]
     traffic = measured_traffic("q16")
+    traffic32 = measured_traffic("fp32")
     line = {
         "metric": METRIC,
         "value": round(q["mlups"], 1),
@@ -322,11 +353,16 @@ def main():
                      "traffic": None if traffic is None else round(traffic / (q["fluid_kernel_ms"] * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": N ** 3 * BYTES_PER_CELL["q16"],
                      "kernel": "fluid_kernel<Q16>", "bytes_per_cell": BYTES_PER_CELL["q16"]},
+        "roofline_valu": valu_roofline("q16", q["fluid_kernel_ms"]),
         "fp32": {"value": round(res["fp32"]["mlups"], 1), "unit": "MLUPS",
                  "ms_per_step": round(res["fp32"]["ms_per_step"], 5),
                  "roofline": {"bound": "hbm", "achieved": round(res["fp32"]["achieved_GBs"], 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(res["fp32"]["hbm_frac"], 4),
-                              "kernel": "fluid_kernel<F32>", "bytes_per_cell": BYTES_PER_CELL["fp32"]}},
+                              "traffic": None if traffic32 is None else
+                              round(traffic32 / (res["fp32"]["fluid_kernel_ms"] * 1e-3) / 1e9, 1),
+                              "traffic_bytes_per_launch": traffic32,
+                              "kernel": "fluid_kernel<F32>", "bytes_per_cell": BYTES_PER_CELL["fp32"]},
+                 "roofline_valu": valu_roofline("fp32", res["fp32"]["fluid_kernel_ms"])},
         "memory_ratio_q16_fp32": res["q16"]["state_bytes"] / res["fp32"]["state_bytes"],
         "adjoint_forward_ratio": extras.get("adjoint", {}).get("ratio"),
         "adjoint": extras.get("adjoint"),

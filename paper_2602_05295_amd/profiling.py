@@ -4,6 +4,7 @@ folder.
     python -m paper_2602_05295_amd.profiling trace  <results.db>  [--title T] [--command C]
     python -m paper_2602_05295_amd.profiling traffic <fetch.db> <write.db> --copy-bytes B
                                              --kernel NAME=FMT:BYTES_PER_LAUNCH [...] [--json OUT]
+    python -m paper_2602_05295_amd.profiling valu <sq.db> --kernel NAME=FMT [...] --json OUT
 
 `trace` prints the per-kernel table of a --kernel-trace --stats run.
 `traffic` turns two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch,
@@ -11,6 +12,8 @@ summed over the counter's instances) into HBM bytes per launch.  Each counter
 is scaled by the factor that makes it read the known size of a plain device
 copy profiled in the same run (the largest __amd_rocclr_copyBuffer
 dispatches): the copy moves B bytes each way.
+`valu` records SQ_INSTS_VALU (wave instructions) per dispatch of the named
+kernels, for the VALU-issue roofline bench.py reports beside the HBM one.
 """
 from __future__ import annotations
 
@@ -43,6 +46,22 @@ def counter_per_dispatch(db: str):
     return out
 
 
+def counter_per_dispatch_named(db: str, counter: str):
+    """{kernel name: [value of `counter` per dispatch]} (instances summed)."""
+    con = sqlite3.connect(db)
+    acc = defaultdict(float)
+    names = {}
+    for disp, kn, v in con.execute(
+            "select dispatch_id, kernel_name, value from counters_collection where counter_name = ?", (counter,)):
+        acc[disp] += v
+        names[disp] = kn
+    con.close()
+    out = defaultdict(list)
+    for disp in sorted(acc):
+        out[names[disp]].append(acc[disp])
+    return out
+
+
 def copy_scale(per: dict, copy_bytes: int) -> float:
     vals = [v for v in per.get("__amd_rocclr_copyBuffer", []) if v * 1024 > copy_bytes / 8]
     if not vals:
@@ -55,6 +74,11 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("db")
+    q = sub.add_parser("valu")
+    q.add_argument("db", help="a --pmc run holding SQ_INSTS_VALU")
+    q.add_argument("--kernel", action="append", default=[], help="NAME=FMT")
+    q.add_argument("--json", required=True)
+    q.add_argument("--kernel-hash", default=None)
     r = sub.add_parser("traffic")
     r.add_argument("fetch_db")
     r.add_argument("write_db")
@@ -63,6 +87,23 @@ def main(argv=None):
     r.add_argument("--json", default=None)
     r.add_argument("--kernel-hash", default=None)
     a = ap.parse_args(argv)
+    if a.cmd == "valu":
+        per = counter_per_dispatch_named(a.db, "SQ_INSTS_VALU")
+        res = {"kernel_hash": a.kernel_hash, "counter": "SQ_INSTS_VALU (wave instructions per dispatch)",
+               "formats": {}}
+        for spec in a.kernel:
+            name, fmt = spec.rsplit("=", 1)
+            vals = per.get(name)
+            if not vals:
+                print(f"missing kernel {name}", file=sys.stderr)
+                return 1
+            res["formats"][fmt] = {"kernel": name, "dispatches": len(vals),
+                                   "valu_instructions_per_launch": round(sum(vals) / len(vals))}
+            print(fmt, res["formats"][fmt])
+        with open(a.json, "w") as fh:
+            json.dump(res, fh, indent=1)
+            fh.write("\n")
+        return 0
     if a.cmd == "trace":
         print("| kernel | calls | total (us) | average (us) | share |")
         print("|---|---:|---:|---:|---:|")
