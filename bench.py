@@ -177,15 +177,16 @@ def adjoint_ratio(n=128, steps=400, every=20):
 
 def channel(steps=20):
     """The 1000x400x400 obstacle channel in 16-bit moments: fluid + boundary
-    passes per step (MLUPS over all cells) and the two kernels' times."""
+    passes per step (MLUPS over all cells) and the two kernels' times.  The
+    fluid starts at rest and the inflow face (u = 0.08) drives it: an
+    impulsive start at u = 0.08 everywhere takes the density behind the
+    obstacles to 0.76 within 50 steps (FP32), below the 16-bit range."""
     import torch
     from paper_2602_05295_amd import workloads as W
     from paper_2602_05295_amd.homelbm import HomeLBM
     nx, ny, nz = 1000, 400, 400
     mask = W.channel_mask(nx, ny, nz, seed=0)
     u = torch.zeros((3, nz, ny, nx), dtype=torch.float32, device="cuda")
-    u[0] = 0.08
-    u[:, torch.from_numpy(mask).cuda().bool()] = 0.0
     rho = torch.ones((nz, ny, nx), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     with HomeLBM((nx, ny, nz), 0.52, mask=mask, fmt="q16", stream=stream.cuda_stream) as s:
@@ -204,7 +205,7 @@ def channel(steps=20):
         nf, ns = s.boundary_counts()
         bad = s.check()
     cells = nx * ny * nz
-    return {"config": "1000x400x400 channel, 16-bit, tau 0.52, inflow 0.08, 300 obstacles",
+    return {"config": "1000x400x400 channel, 16-bit, tau 0.52, inflow 0.08 into fluid at rest, 300 obstacles",
             "solid_fraction": round(float(mask.mean()), 4), "boundary_fluid_cells": nf, "boundary_solid_cells": ns,
             "mlups": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
             "fluid_kernel_ms": round(prof["fluid_ms"] / prof["fluid_launches"], 4),
