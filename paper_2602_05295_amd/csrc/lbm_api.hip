@@ -125,19 +125,19 @@ int build_list(lbm_ctx* c) {
     run += uint32_t(__builtin_popcountll(hmask[k]));
   }
   if (run != cnt[0]) return fail(c, LBM_ERR_DEVICE, "boundary list: bitmap and count disagree");
-  std::vector<uint4> hpack(nchunks);
+  std::vector<uint4> hpack(nchunks + 1, make_uint4(0u, 0u, 0u, 0u));  // one padding entry
   for (size_t k = 0; k < nchunks; ++k)
     hpack[k] = make_uint4(uint32_t(hmask[k]), uint32_t(hmask[k] >> 32), hbase[k], 0u);
   e = hipMemcpy(c->d_lbase, hbase.data(), nchunks * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&c->d_lpack, nchunks * sizeof(uint4));
-  if (e == hipSuccess) e = hipMemcpy(c->d_lpack, hpack.data(), nchunks * sizeof(uint4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_lpack, (nchunks + 1) * sizeof(uint4));
+  if (e == hipSuccess) e = hipMemcpy(c->d_lpack, hpack.data(), (nchunks + 1) * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(c, e, "uploading list offsets");
   const int64_t total = int64_t(cnt[0]) + cnt[1];
   if (total > 0) {
     e = hipMalloc(&c->d_cells, size_t(total) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_bits, size_t(total) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_yz, size_t(std::max<uint32_t>(cnt[0], 1)) * 4);
-    if (e == hipSuccess) e = hipMalloc(&c->d_side, size_t(std::max<uint32_t>(cnt[0], 1)) * 40);
+    if (e == hipSuccess) e = hipMalloc(&c->d_side, size_t(std::max<uint32_t>(cnt[0], 1)) * 48);
     if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(boundary list)");
     // fluid entries in raster order, solid entries after them
     e = hipMemsetAsync(c->d_counters, 0, 4 * sizeof(uint32_t), c->stream);
@@ -503,7 +503,7 @@ int lbm_memory_bytes(const lbm_ctx* c, size_t* sb, size_t* tb) {
   const size_t s = 2 * state_bytes(c);
   if (sb) *sb = s;
   if (tb)
-    *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 44 +
+    *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 52 +
           (c->d_lmask ? size_t((c->N + 63) / 64) * 28 : 0) + 4 * 4 + 8;
   return LBM_OK;
 }

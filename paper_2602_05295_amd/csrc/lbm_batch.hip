@@ -120,14 +120,13 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
     BRaw<FMT> nxt1{};
     if (active) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(za - 1, nz))) * 4u);
     const bool keep = own && a.lc.side != nullptr;  // listed cells to look for
-    uint4 lw = make_uint4(0, 0, 0, 0);              // packed bitmap word of the cell stored next
+    ListedPair lw{};                                // packed bitmap words of the cells stored next
     for (int p = za - 1; p <= zb; ++p) {
       const BRaw<FMT> cur = nxt1;
       if (active && p + 1 <= zb) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(p + 1, nz))) * 4u);
-      const uint4 lw_cur = lw;
+      const ListedPair lw_cur = lw;
       if (keep && p >= za && p < zb) {  // plane p is stored in the next iteration
-        const uint32_t gc = D.off + rowc + plane * uint32_t(p);
-        lw = a.lc.lpack[gc >> 6];
+        lw = listed_pair(a.lc, D.off + rowc + plane * uint32_t(p));
       }
 
       float f0[8];
@@ -203,13 +202,8 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
           if (own) {
             const uint32_t cell = rowc + plane * uint32_t(p - 1);
             bstore<FMT>(a, (D.off + cell) * 4u, cell, key, dith, dr, j, P);
-            const int slot = keep ? listed_slot_in(lw_cur, D.off + cell) : -1;
-            if (slot >= 0) {
-              // a listed cell: its unrounded moments go to its side-buffer slot
-              const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
-#pragma unroll
-              for (int k = 0; k < 10; ++k) a.lc.side[size_t(k) * a.lc.nside + uint32_t(slot)] = v[k];
-            }
+            const int slot = keep ? listed_slot_in(listed_word(lw_cur, D.off + cell), D.off + cell) : -1;
+            if (slot >= 0) side_store(a.lc.side, uint32_t(slot), dr, j, P);  // a listed cell's unrounded moments
           }
         }
 #pragma unroll

@@ -378,16 +378,16 @@ int build_lists(lbm_batch* b) {
     run += uint32_t(__builtin_popcountll(hmask[k]));
   }
   if (int64_t(run) != nf_all) return bfail(b, LBM_ERR_DEVICE, "boundary list: bitmap and counts disagree");
-  std::vector<uint4> hpack(nchunks);
+  std::vector<uint4> hpack(nchunks + 1, make_uint4(0u, 0u, 0u, 0u));  // one padding entry
   for (size_t k = 0; k < nchunks; ++k)
     hpack[k] = make_uint4(uint32_t(hmask[k]), uint32_t(hmask[k] >> 32), hbase[k], 0u);
   e = hipMemcpy(b->d_lbase, hbase.data(), nchunks * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&b->d_lpack, nchunks * sizeof(uint4));
-  if (e == hipSuccess) e = hipMemcpy(b->d_lpack, hpack.data(), nchunks * sizeof(uint4), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&b->d_lpack, (nchunks + 1) * sizeof(uint4));
+  if (e == hipSuccess) e = hipMemcpy(b->d_lpack, hpack.data(), (nchunks + 1) * sizeof(uint4), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&b->d_cells, size_t(total) * 4);
   if (e == hipSuccess) e = hipMalloc(&b->d_bits, size_t(total) * 4);
   if (e == hipSuccess) e = hipMalloc(&b->d_yz, size_t(std::max<int64_t>(nf_all, 1)) * 4);
-  if (e == hipSuccess) e = hipMalloc(&b->d_side, size_t(std::max<int64_t>(nf_all, 1)) * 40);
+  if (e == hipSuccess) e = hipMalloc(&b->d_side, size_t(std::max<int64_t>(nf_all, 1)) * 48);
   if (e == hipSuccess) e = hipMalloc(&b->d_dom, size_t(total) * 2);
   if (e != hipSuccess) return bhip(b, e, "hipMalloc(boundary list)");
   // fluid entries in global cell order (so each domain's are contiguous), then solid entries
@@ -884,7 +884,7 @@ int lbm_batch_memory_bytes(const lbm_batch* b, size_t* state_bytes, size_t* tota
   if (state_bytes) *state_bytes = s;
   if (total_bytes)
     *total_bytes = s + (b->d_mask ? size_t(b->N) : 0) + size_t(b->n_fluid_b + b->n_solid_b) * 10 +
-                   size_t(b->n_fluid_b) * 44 + (b->d_lmask ? size_t((b->N + 63) / 64) * 28 : 0) +
+                   size_t(b->n_fluid_b) * 52 + (b->d_lmask ? size_t((b->N + 63) / 64) * 28 : 0) +
                    b->plan.segs.size() * sizeof(BatchSeg) + b->plan.wg_first.size() * 4 +
                    size_t(b->count) * sizeof(BatchDomain) + 32;
   return LBM_OK;

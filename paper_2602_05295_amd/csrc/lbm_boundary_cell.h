@@ -184,8 +184,7 @@ __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t ce
   const int y = int(yz & 0xFFFFu), z = int(yz >> 16);
   const int x = int(cell - uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z)));
   float m[10];
-#pragma unroll
-  for (int k = 0; k < 10; ++k) m[k] = a.lc.side[size_t(k) * a.lc.nside + e];
+  side_load(a.lc.side, e, m);
   float Aown[NA];
   source_coeffs<FMT>(a, cell, false, Aown);
   uint32_t bb = b & 0x7FFFFFFu & ~(1u << 13);

@@ -100,15 +100,12 @@ __device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, 
 }
 
 // A listed cell's unrounded moments go to its slot of the side buffer, where
-// the boundary pass picks them up.  w: the cell's packed bitmap word, loaded
-// a plane ahead.
-__device__ inline void keep_listed(const ListedCells& lc, uint32_t cell, const uint4& w, float dr, const float j[3],
-                                   const float P[6]) {
-  const int slot = listed_slot_in(w, cell);
-  if (slot < 0) return;
-  const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
-#pragma unroll
-  for (int k = 0; k < 10; ++k) lc.side[size_t(k) * lc.nside + uint32_t(slot)] = v[k];
+// the boundary pass picks them up.  pr: the packed bitmap words of the
+// wavefront's cells, loaded a plane ahead.
+__device__ inline void keep_listed(const ListedCells& lc, uint32_t cell, const ListedPair& pr, float dr,
+                                   const float j[3], const float P[6]) {
+  const int slot = listed_slot_in(listed_word(pr, cell), cell);
+  if (slot >= 0) side_store(lc.side, uint32_t(slot), dr, j, P);
 }
 
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -160,19 +157,21 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     for (int g = 0; g < 6; ++g) wA[g] = wB[g] = zA[g] = zB[g] = 0.0f;
     Raw<FMT> bufA = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(za - 1, nz))) * 4u);
     Raw<FMT> bufB;
-    const bool keep = own && a.lc.side != nullptr;  // listed cells to look for
-    uint4 lwA = make_uint4(0, 0, 0, 0), lwB = make_uint4(0, 0, 0, 0);
+    // listed cells to look for: a wavefront-uniform condition, so that the
+    // bitmap words stay in scalar registers and empty words skip everything
+    const bool keep = compute && a.lc.side != nullptr;
+    const uint32_t row0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: the row's first own cell
+    ListedPair lwA{}, lwB{};
 
     // One plane p: cur holds its state, nxt receives plane p + 1's; wp2 holds
     // the fp of plane p - 2 and receives this plane's fp; w0in holds the f0 of
     // plane p - 1, w0out receives this plane's; lw_cur belongs to the cell of
     // plane p - 1, lw_nxt receives that of plane p.
     auto plane_step = [&](int p, const Raw<FMT>& cur, Raw<FMT>& nxt, float (&wp2)[6], const float (&w0)[6],
-                          float (&w0out)[6], const uint4 lw_cur, uint4& lw_nxt) {
+                          float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt) {
       if (p + 1 <= zb) nxt = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
       if (keep && p >= za && p < zb) {  // plane p is stored in the next step
-        const uint32_t c = row + plane * uint32_t(p);
-        lw_nxt = a.lc.lpack[c >> 6];
+        lw_nxt = listed_pair(a.lc, row0 + plane * uint32_t(p));
       }
 
       const CellIn c = decode<FMT>(cur);
@@ -270,7 +269,8 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
           if (own) {
             const uint32_t cell = row + plane * uint32_t(p - 1);
             store_cell<FMT>(a, cell, dr, j, P);
-            if (keep) keep_listed(a.lc, cell, lw_cur, dr, j, P);
+            if (keep && (lw_cur.a.x | lw_cur.a.y | lw_cur.b.x | lw_cur.b.y) != 0u)
+              keep_listed(a.lc, cell, lw_cur, dr, j, P);
           }
         }
 #pragma unroll

@@ -24,9 +24,33 @@ struct Geometry {
 // marked cells before it in that word.  One 16-byte load gives both.
 struct ListedCells {
   const uint4* lpack;
-  float* side;      // 10 planes of nside floats: the fluid pass's unrounded moments of each listed cell
+  float* side;      // nside records of 12 floats (48 B): the fluid pass's unrounded moments of each listed cell
   uint32_t nside;
 };
+
+// Side-buffer record of one listed cell: (rho - 1, j, P) and two pad floats,
+// written and read as three 16-byte words.
+__device__ inline void side_store(float* side, uint32_t slot, float dr, const float j[3], const float P[6]) {
+  float4* r = reinterpret_cast<float4*>(side) + size_t(slot) * 3;
+  r[0] = make_float4(dr, j[0], j[1], j[2]);
+  r[1] = make_float4(P[0], P[1], P[2], P[3]);
+  r[2] = make_float4(P[4], P[5], 0.0f, 0.0f);
+}
+
+__device__ inline void side_load(const float* side, uint32_t slot, float m[10]) {
+  const float4* r = reinterpret_cast<const float4*>(side) + size_t(slot) * 3;
+  const float4 a = r[0], b = r[1], c = r[2];
+  m[0] = a.x;
+  m[1] = a.y;
+  m[2] = a.z;
+  m[3] = a.w;
+  m[4] = b.x;
+  m[5] = b.y;
+  m[6] = b.z;
+  m[7] = b.w;
+  m[8] = c.x;
+  m[9] = c.y;
+}
 
 struct StepParams {
   const void* in[10];  // state planes read (FP32: 10 float planes, Q16: 5 word planes)
@@ -38,6 +62,23 @@ struct StepParams {
   float u_in[3];
   ListedCells lc;      // lc.side == nullptr: no listed cells
 };
+
+// The packed words of the 64-cell blocks w0 and w0 + 1 (lpack holds one
+// padding entry at the end), for a wavefront whose stored cells are
+// consecutive and start in block w0: those cells lie in these two blocks.
+// The block index is taken from the first active lane, so the two loads are
+// scalar ones (no vector memory traffic).
+struct ListedPair {
+  uint4 a, b;
+  uint32_t w0;
+};
+
+__device__ inline ListedPair listed_pair(const ListedCells& lc, uint32_t first_cell) {
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane(first_cell >> 6);
+  return ListedPair{lc.lpack[w0], lc.lpack[w0 + 1], w0};
+}
+
+__device__ inline const uint4& listed_word(const ListedPair& pr, uint32_t c) { return (c >> 6) == pr.w0 ? pr.a : pr.b; }
 
 // Slot of cell c given its packed word w, or -1 if c is not listed.
 __device__ inline int listed_slot_in(const uint4& w, uint32_t c) {
