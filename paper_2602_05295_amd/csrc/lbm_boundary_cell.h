@@ -182,7 +182,6 @@ template <int FMT>
 __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t cell, uint32_t b, uint32_t yz) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int y = int(yz & 0xFFFFu), z = int(yz >> 16);
-  const int x = int(cell - uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z)));
   float m[10];
   side_load(a.lc.side, e, m);
   float Aown[NA];

@@ -1,12 +1,12 @@
 // lbm_fluid.hip -- the fused fluid pass (Sec. 4.2, Alg. 2) for gfx950.
 //
 // The step factorises into three 1D "reconstruct -> shift -> project" passes
-// (lbm_device.h).  One workgroup of 15 wavefronts owns a tile of 64 x 12
-// output cells of an x-y plane and marches through z:
-//   - 14 row wavefronts: one 64-cell row each (a coalesced 256 B or 128 B
-//     row per plane), the 12 output rows plus one halo row above and below;
-//   - 1 column wavefront: the halo cells at x0 - 1 and x0 + 64 of those 15
-//     rows, so no lane of the row wavefronts is spent on halo cells.
+// (lbm_device.h).  One workgroup of R + 3 wavefronts owns a tile of 64 x R
+// output cells of an x-y plane (R = 8, 10, 12 or 13) and marches through z:
+//   - R + 2 row wavefronts: one 64-cell row each (a coalesced 256 B or 128 B
+//     row per plane), the R output rows plus one halo row above and below;
+//   - 1 column wavefront: the halo cells at x0 - 1 and x0 + 64 of those
+//     R + 2 rows, so no lane of the row wavefronts is spent on halo cells.
 // Per plane every cell is loaded once and collided (App. A); then
 //   y pass: reconstruct the y movers of 8 groups, exchange them through LDS
 //           (the halo rows stop here, having paid for a load, a collision and
@@ -16,7 +16,8 @@
 //   z pass: 6 groups whose z neighbours are the previous and next planes of
 //           the march, held in registers.
 // Only the ten new moments are written.  The next plane's state is loaded
-// while the current one is computed.
+// while the current one is computed; a plane's new moments are stored at the
+// start of the following plane step, before its loads (see plane_step).
 //
 // Work items are (tile, z segment) pairs.  Every tile's z range is cut into
 // the same S equal segments, so all items of a wave start on the same plane
@@ -34,9 +35,8 @@
 
 namespace lbm {
 
-// 16-bit states: two planes per trip of the z march, with the paired buffers'
-// roles swapped, so no register is copied from one plane to the next (6% on
-// the 16-bit pass; the FP32 pass, bound by memory, is 2% faster without it).
+// Two planes per trip of the z march, with the paired buffers' roles swapped,
+// so no register is copied from one plane to the next (3% on both formats).
 #ifndef LBM_PLANE_PAIRS
 #define LBM_PLANE_PAIRS 1
 #endif
@@ -73,6 +73,16 @@ __device__ inline Raw<FMT> load_raw(const StepParams& a, uint32_t off) {
     for (int k = 0; k < 5; ++k) r.v[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + off);
   }
   return r;
+}
+
+// Marks the point where a plane's state must have arrived: an empty asm that
+// reads its registers (so the wait for the loads is placed here) and that no
+// memory operation may cross (so none issued after it is waited for).
+template <int FMT>
+__device__ inline void state_arrived(const Raw<FMT>& r) {
+  constexpr int K = FMT == FMT_F32 ? 10 : 5;
+#pragma unroll
+  for (int k = 0; k < K; ++k) asm volatile("" : : "v"(r.v[k]) : "memory");
 }
 
 template <int FMT>
@@ -149,9 +159,9 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
 
     // z window (fp of planes p - 2 / p - 1, f0 of plane p - 1), the state of
     // the next plane in flight while the current one is computed, and the
-    // listed-cell bitmap word / prefix count of the cell stored next.  The
-    // plane loop runs two planes per trip with the roles of the paired
-    // buffers swapped, so no register is copied from one plane to the next.
+    // listed-cell bitmap words of the cell stored next.  The plane loop runs
+    // two planes per trip with the roles of the paired buffers swapped, so no
+    // register is copied from one plane to the next.
     float wA[6], wB[6], zA[6], zB[6];
 #pragma unroll
     for (int g = 0; g < 6; ++g) wA[g] = wB[g] = zA[g] = zB[g] = 0.0f;
@@ -162,17 +172,30 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     const bool keep = compute && a.lc.side != nullptr;
     const uint32_t row0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: the row's first own cell
     ListedPair lwA{}, lwB{};
+    // New moments of the plane finished by the previous step.  They are
+    // stored at the start of the next step, after its state has arrived and
+    // before its loads are issued: then no store is issued between a plane's
+    // loads and their use, and the wait for the loads is a wait for them
+    // alone (a store issued later would have to complete as well).
+    float sdr = 0.0f, sj[3] = {0.0f, 0.0f, 0.0f}, sP[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    auto store_plane = [&](int ps, const ListedPair& lw) {
+      if (own) {
+        const uint32_t cell = row + plane * uint32_t(ps);
+        store_cell<FMT>(a, cell, sdr, sj, sP);
+        if (keep && (lw.a.x | lw.a.y | lw.b.x | lw.b.y) != 0u) keep_listed(a.lc, cell, lw, sdr, sj, sP);
+      }
+    };
 
     // One plane p: cur holds its state, nxt receives plane p + 1's; wp2 holds
     // the fp of plane p - 2 and receives this plane's fp; w0in holds the f0 of
     // plane p - 1, w0out receives this plane's; lw_cur belongs to the cell of
-    // plane p - 1, lw_nxt receives that of plane p.
+    // plane p - 2 (stored now), lw_nxt receives that of plane p - 1.
     auto plane_step = [&](int p, const Raw<FMT>& cur, Raw<FMT>& nxt, float (&wp2)[6], const float (&w0)[6],
                           float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt) {
+      state_arrived<FMT>(cur);
+      if (p - 2 >= za) store_plane(p - 2, lw_cur);
+      if (keep && p - 1 >= za && p - 1 < zb) lw_nxt = listed_pair(a.lc, row0 + plane * uint32_t(p - 1));
       if (p + 1 <= zb) nxt = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
-      if (keep && p >= za && p < zb) {  // plane p is stored in the next step
-        lw_nxt = listed_pair(a.lc, row0 + plane * uint32_t(p));
-      }
 
       const CellIn c = decode<FMT>(cur);
       float Nn[6];
@@ -258,20 +281,13 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
         recon3(X20[0], X20[1], X20[2], zf0[3], zfp[3], zfm[3]);
         recon3(X11[0], X11[1], X11[2], zf0[4], zfp[4], zfm[4]);
         recon3(X02[0], X02[1], X02[2], zf0[5], zfp[5], zfm[5]);
-        if (p > za) {  // plane p - 1 is complete
-          float dr, j[3], P[6];
-          proj3(w0[0], wp2[0], zfm[0], dr, j[2], P[2]);  // (0,0,c): rho-1, jz, Pzz
-          proj2(w0[1], wp2[1], zfm[1], j[0], P[4]);      // (1,0,c): jx, Pxz
-          proj2(w0[2], wp2[2], zfm[2], j[1], P[5]);      // (0,1,c): jy, Pyz
-          P[0] = proj1(w0[3], wp2[3], zfm[3]);           // Pxx
-          P[3] = proj1(w0[4], wp2[4], zfm[4]);           // Pxy
-          P[1] = proj1(w0[5], wp2[5], zfm[5]);           // Pyy
-          if (own) {
-            const uint32_t cell = row + plane * uint32_t(p - 1);
-            store_cell<FMT>(a, cell, dr, j, P);
-            if (keep && (lw_cur.a.x | lw_cur.a.y | lw_cur.b.x | lw_cur.b.y) != 0u)
-              keep_listed(a.lc, cell, lw_cur, dr, j, P);
-          }
+        if (p > za) {  // plane p - 1 is complete; stored in the next step
+          proj3(w0[0], wp2[0], zfm[0], sdr, sj[2], sP[2]);  // (0,0,c): rho-1, jz, Pzz
+          proj2(w0[1], wp2[1], zfm[1], sj[0], sP[4]);       // (1,0,c): jx, Pxz
+          proj2(w0[2], wp2[2], zfm[2], sj[1], sP[5]);       // (0,1,c): jy, Pyz
+          sP[0] = proj1(w0[3], wp2[3], zfm[3]);             // Pxx
+          sP[3] = proj1(w0[4], wp2[4], zfm[4]);             // Pxy
+          sP[1] = proj1(w0[5], wp2[5], zfm[5]);             // Pyy
         }
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
@@ -281,7 +297,11 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
       }
     };
 
-    if constexpr (FMT == FMT_Q16 && LBM_PLANE_PAIRS) {
+    // The last step (plane zb) leaves the moments of plane zb - 1, whose
+    // bitmap words it loaded into lwB when it ran as the first plane of a
+    // trip (lwA otherwise, and always lwA in the one-plane loop).
+    bool last_in_b = false;
+    if constexpr (LBM_PLANE_PAIRS) {
       // buffers at the start of a trip: state in bufA, fp(p - 2) in wA, fp(p - 1) in wB, f0(p - 1) in zA
       for (int p = za - 1; p <= zb; p += 2) {
         plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
@@ -289,6 +309,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
         if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA);
         // now fp(p) in wA, fp(p + 1) in wB, f0(p + 1) in zA: the trip's starting roles
       }
+      last_in_b = ((zb - za) & 1) != 0;  // plane zb ran first in its trip
     } else {
       // one plane per trip, the roles restored by copies
       for (int p = za - 1; p <= zb; ++p) {
@@ -303,6 +324,12 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
         }
         lwA = lwB;
       }
+    }
+    if (zb - 1 >= za) {
+      if (last_in_b)
+        store_plane(zb - 1, lwB);
+      else
+        store_plane(zb - 1, lwA);
     }
   }
 }
