@@ -152,6 +152,21 @@ size_t lbm_raw_bytes(const lbm_ctx* ctx);
 int lbm_get_raw(lbm_ctx* ctx, void* out, size_t bytes, int on_device);
 int lbm_set_raw(lbm_ctx* ctx, const void* in, size_t bytes, int on_device);
 
+/*
+ * One time step from a caller-owned raw state to another (Alg. 2 followed by
+ * the boundary pass, as one lbm_step iteration): in and out are device
+ * pointers to lbm_raw_bytes() bytes each in the lbm_get_raw layout, and must
+ * not overlap (LBM_ERR_INVALID_ARG otherwise).  in must hold the rest state at
+ * the solid cells next to fluid, as every state that lbm_get_raw returns does.
+ * Uses the context's geometry, mask, tau and options, draws the dither of the
+ * context's step count and advances that count by one.  The context's own
+ * state is neither read nor written, and no health scan is made.
+ * Asynchronous on the context stream; the caller keeps both buffers alive
+ * until the step has run.  Meant for rollouts that keep every state, such as
+ * the recomputation of a checkpointed segment before its adjoint steps.
+ */
+int lbm_step_into(lbm_ctx* ctx, const void* in, void* out);
+
 /* Step counter used by the dither. */
 int lbm_get_step_count(const lbm_ctx* ctx, uint64_t* t);
 int lbm_set_step_count(lbm_ctx* ctx, uint64_t t);

@@ -4,10 +4,11 @@ library's forward step (lbm_step) and its hand-written adjoint
 
 forward:  m(0) = equilibrium(rho0, u0); a raw-state checkpoint every k steps;
           T steps; returns the final moment field (10, nz, ny, nx).
-backward: for each checkpointed segment, last first: restore the checkpoint,
-          recompute and keep the segment's states, run the adjoint steps
-          backwards through them; finally map lam(0) through the equilibrium
-          initialisation to d/du0 and d/drho0.
+backward: for each checkpointed segment, last first: recompute the
+          segment's states from its checkpoint (lbm_step_into, each written
+          to its own tensor), run the adjoint steps backwards through them;
+          finally map lam(0) through the equilibrium initialisation to d/du0
+          and d/drho0.
 Memory: T/k checkpoints plus k states, each 40 B per cell.
 All arithmetic runs in the library; torch provides device memory and the stream.
 """
@@ -54,12 +55,12 @@ class _Rollout(torch.autograd.Function):
         nseg = len(ctx.cps)
         for s in range(nseg - 1, -1, -1):
             k = min(every, nsteps - s * every)
-            sim.set_raw(ctx.cps[s])
+            # recompute the segment's states straight into their own tensors
+            sim.step_count = ctx.t0 + s * every
             states = [ctx.cps[s]]
             for _ in range(k - 1):
-                sim.step(1)
                 st = torch.empty_like(lam)
-                sim.get_raw(st)
+                sim.step_into(states[-1], st)
                 states.append(st)
             for st in reversed(states):
                 sim.adjoint_step(st, lam, spare)

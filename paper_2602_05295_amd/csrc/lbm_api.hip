@@ -197,9 +197,9 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   return p;
 }
 
-// One step: fluid pass then boundary pass, buffers swapped.
-int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
-  const StepParams p = step_params(c, c->buf[c->cur], c->buf[1 - c->cur]);
+// One step from in to out: fluid pass then boundary pass.
+int enqueue_pass(lbm_ctx* c, const void* in, void* out, hipEvent_t ev[4]) {
+  const StepParams p = step_params(c, in, out);
   hipError_t e = hipSuccess;
   if (ev) e = hipEventRecord(ev[0], c->stream);
   if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->opt.tile_rows, c->stream);
@@ -214,9 +214,15 @@ int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
-  c->cur = 1 - c->cur;
   c->t += 1;
   return LBM_OK;
+}
+
+// One step of the context's own state, buffers swapped.
+int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
+  const int r = enqueue_pass(c, c->buf[c->cur], c->buf[1 - c->cur], ev);
+  if (r == LBM_OK) c->cur = 1 - c->cur;
+  return r;
 }
 
 int scan_health(lbm_ctx* c, uint64_t* bad) {
@@ -434,6 +440,19 @@ int lbm_step(lbm_ctx* c, int n) {
     if (bad) return fail(c, LBM_ERR_UNSTABLE, "state holds " + std::to_string(bad) + " non-finite or saturated values");
   }
   return LBM_OK;
+}
+
+int lbm_step_into(lbm_ctx* c, const void* in, void* out) {
+  if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
+  if (!in || !out) return fail(c, LBM_ERR_INVALID_ARG, "NULL state buffer");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+  const uintptr_t n = state_bytes(c);
+  if (a < b + n && b < a + n) return fail(c, LBM_ERR_INVALID_ARG, "in and out overlap");
+  if (!c->list_built) {
+    const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  return enqueue_pass(c, in, out, nullptr);
 }
 
 int lbm_get_moments(lbm_ctx* c, float* m, int on_device) {

@@ -82,6 +82,19 @@ __device__ inline void bstore(const BatchStepParams& a, uint32_t byte_off, uint3
 
 __device__ inline int wrap1b(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// The point where a plane's state must have arrived: an empty asm that reads
+// its registers and that no memory operation may cross.  The plane loop below
+// stores a plane's moments at the start of the next iteration, after this
+// point and before that iteration's loads, so the wait covers those loads
+// alone (a store issued after them would have to complete as well, since one
+// counter retires loads and stores in issue order).
+template <int FMT>
+__device__ inline void bstate_arrived(const BRaw<FMT>& r) {
+  constexpr int K = FMT == FMT_F32 ? 10 : 5;
+#pragma unroll
+  for (int k = 0; k < K; ++k) asm volatile("" : : "v"(r.v[k]) : "memory");
+}
+
 template <int FMT, int NT>
 __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
   __shared__ float ly[16][NT];  // y movers (+, -) of 8 groups
@@ -121,13 +134,23 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
     if (active) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(za - 1, nz))) * 4u);
     const bool keep = own && a.lc.side != nullptr;  // listed cells to look for
     ListedPair lw{};                                // packed bitmap words of the cells stored next
+    // new moments of the plane finished by the previous iteration
+    float sdr = 0.0f, sj[3] = {0.0f, 0.0f, 0.0f}, sP[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    auto store_plane = [&](int ps, const ListedPair& lws) {
+      if (own) {
+        const uint32_t cell = rowc + plane * uint32_t(ps);
+        bstore<FMT>(a, (D.off + cell) * 4u, cell, key, dith, sdr, sj, sP);
+        const int slot = keep ? listed_slot_in(listed_word(lws, D.off + cell), D.off + cell) : -1;
+        if (slot >= 0) side_store(a.lc.side, uint32_t(slot), sdr, sj, sP);  // a listed cell's unrounded moments
+      }
+    };
     for (int p = za - 1; p <= zb; ++p) {
       const BRaw<FMT> cur = nxt1;
+      bstate_arrived<FMT>(cur);
+      const ListedPair lw_cur = lw;  // words of plane p - 2
+      if (p - 2 >= za) store_plane(p - 2, lw_cur);
+      if (keep && p - 1 >= za && p - 1 < zb) lw = listed_pair(a.lc, D.off + rowc + plane * uint32_t(p - 1));
       if (active && p + 1 <= zb) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(p + 1, nz))) * 4u);
-      const ListedPair lw_cur = lw;
-      if (keep && p >= za && p < zb) {  // plane p is stored in the next iteration
-        lw = listed_pair(a.lc, D.off + rowc + plane * uint32_t(p));
-      }
 
       float f0[8];
       if (active) {
@@ -191,20 +214,13 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
         recon3(X20[0], X20[1], X20[2], zf0[3], zfp[3], zfm[3]);
         recon3(X11[0], X11[1], X11[2], zf0[4], zfp[4], zfm[4]);
         recon3(X02[0], X02[1], X02[2], zf0[5], zfp[5], zfm[5]);
-        if (p > za) {  // plane p - 1 is complete
-          float dr, j[3], P[6];
-          proj3(w0[0], wp2[0], zfm[0], dr, j[2], P[2]);  // (0,0,c): rho-1, jz, Pzz
-          proj2(w0[1], wp2[1], zfm[1], j[0], P[4]);      // (1,0,c): jx, Pxz
-          proj2(w0[2], wp2[2], zfm[2], j[1], P[5]);      // (0,1,c): jy, Pyz
-          P[0] = proj1(w0[3], wp2[3], zfm[3]);           // Pxx
-          P[3] = proj1(w0[4], wp2[4], zfm[4]);           // Pxy
-          P[1] = proj1(w0[5], wp2[5], zfm[5]);           // Pyy
-          if (own) {
-            const uint32_t cell = rowc + plane * uint32_t(p - 1);
-            bstore<FMT>(a, (D.off + cell) * 4u, cell, key, dith, dr, j, P);
-            const int slot = keep ? listed_slot_in(listed_word(lw_cur, D.off + cell), D.off + cell) : -1;
-            if (slot >= 0) side_store(a.lc.side, uint32_t(slot), dr, j, P);  // a listed cell's unrounded moments
-          }
+        if (p > za) {  // plane p - 1 is complete; stored in the next iteration
+          proj3(w0[0], wp2[0], zfm[0], sdr, sj[2], sP[2]);  // (0,0,c): rho-1, jz, Pzz
+          proj2(w0[1], wp2[1], zfm[1], sj[0], sP[4]);       // (1,0,c): jx, Pxz
+          proj2(w0[2], wp2[2], zfm[2], sj[1], sP[5]);       // (0,1,c): jy, Pyz
+          sP[0] = proj1(w0[3], wp2[3], zfm[3]);             // Pxx
+          sP[3] = proj1(w0[4], wp2[4], zfm[4]);             // Pxy
+          sP[1] = proj1(w0[5], wp2[5], zfm[5]);             // Pyy
         }
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
@@ -214,6 +230,7 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
         }
       }
     }
+    if (zb - 1 >= za) store_plane(zb - 1, lw);
   }
 }
 

@@ -88,6 +88,7 @@ def lib():
     L.lbm_set_moments.argtypes = [vp, vp, i]
     L.lbm_set_equilibrium.argtypes = [vp, vp, vp, i]
     L.lbm_step.argtypes = [vp, i]
+    L.lbm_step_into.argtypes = [vp, vp, vp]
     L.lbm_get_moments.argtypes = [vp, vp, i]
     L.lbm_raw_bytes.argtypes = [vp]
     L.lbm_raw_bytes.restype = sz
@@ -298,6 +299,17 @@ class HomeLBM:
     # -- stepping
     def step(self, n=1):
         self._check(lib().lbm_step(self._h, int(n)))
+
+    def step_into(self, raw_in, raw_out):
+        """One step from the raw state raw_in to raw_out (device tensors in the
+        get_raw layout); the context's own state is left as it is."""
+        dt = np.float32 if self.fmt == FP32 else np.uint32
+        n = (10 if self.fmt == FP32 else 5) * self.N
+        p1, d1, k1 = _ptr(raw_in, dt, n)
+        p2, d2, k2 = _ptr(raw_out, dt, n)
+        if not (d1 and d2):
+            raise ValueError("step_into takes device tensors")
+        self._check(lib().lbm_step_into(self._h, p1, p2))
 
     def synchronize(self):
         self._check(lib().lbm_synchronize(self._h))

@@ -380,3 +380,43 @@ def test_set_raw_puts_listed_solid_cells_back_at_rest(H, fmt):
     fl = mask == 0
     assert np.array_equal(got[:, fl], ref[:, fl])
 
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+@pytest.mark.parametrize("inflow", [False, True])
+def test_step_into_matches_step(H, fmt, inflow):
+    """lbm_step_into from a raw state gives the same state as lbm_step from
+    it (same dither, same boundary handling), and leaves the context's own
+    state and the input buffer alone."""
+    import torch
+    dims = (70, 23, 11)
+    _note("step_into", fmt, "inflow", inflow)
+    mask = W.sphere_mask(*dims, phi=0.08, rmin=1.5, rmax=3.0, seed=21)
+    if inflow:
+        mask = _faces_clear(mask)
+    m = W.random_moments(*dims, seed=4, dj=0.02, dp=0.003).astype(np.float32)
+    with H.HomeLBM(dims, 0.58, mask=mask, fmt=fmt) as s:
+        s.set_options(dither_mode=1, seed=3, inflow=inflow, u_in=(0.05, 0.0, 0.01))
+        s.set_moments(m)
+        s.step(2)
+        t = s.step_count
+        raw0 = s.get_raw().copy()
+        s.step(3)
+        want = s.get_raw().copy()
+        tt = torch.float32 if fmt == "fp32" else torch.int32
+        a = torch.from_numpy(raw0.view(np.float32 if fmt == "fp32" else np.int32)).cuda()
+        b, c = torch.empty_like(a), torch.empty_like(a)
+        assert a.dtype == tt
+        s.step_count = t
+        s.step_into(a, b)
+        s.step_into(b, c)
+        s.step_into(c, b)
+        assert s.step_count == t + 3
+        own = s.get_raw()
+        torch.cuda.synchronize()
+        got = b.cpu().numpy().view(want.dtype)
+        assert np.array_equal(got, want)
+        assert np.array_equal(a.cpu().numpy().view(raw0.dtype), raw0)
+        assert np.array_equal(own, want)  # the context's own state: still the state after its 5 steps
+        with pytest.raises(H.LBMError):
+            s.step_into(a, a)
