@@ -7,7 +7,8 @@
  *   - state: per cell the ten moments of Eq. (rho_u_stress), Sec. 3.1:
  *     rho, j = rho u (3) and P = rho S (6, S the Hermite second moment
  *     sum (c c - cs^2 delta) f / rho), stored after streaming (Alg. 2);
- *   - step: moment-space collision (App. A, force-free) -> third-order Hermite
+ *   - step: moment-space collision (App. A, with an optional uniform body
+ *     force) -> third-order Hermite
  *     reconstruction of f+ (Eq. three_order_f, Sec. 3.2) -> pull streaming
  *     f_i(x) = f+_i(x - c_i) -> projection back to moments (Sec. 4.2, Alg. 2);
  *   - boundaries in a separate pass over a compacted list of boundary cells
@@ -82,6 +83,11 @@ typedef struct lbm_options {
                          (FP32) or any code sits at 0 or 65535 (Q16) */
   int tile_rows;      /* fluid-pass tile height: 0 (default) picks one from the grid
                          shape; 8, 10, 12 or 13 force it.  Results do not depend on it. */
+  float force[3];     /* uniform body force F per cell and step, lattice units (App. A
+                         with its force terms; the stored momentum holds F/2 as in
+                         Eq. rho_u_stress).  Default 0; each |F_a| <= 0.01.  Not
+                         supported by lbm_adjoint_step (LBM_ERR_UNSUPPORTED) nor by
+                         batches (force must be 0 there). */
 } lbm_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -184,8 +190,8 @@ int lbm_boundary_counts(const lbm_ctx* ctx, int64_t* fluid_cells, int64_t* solid
 int lbm_check(lbm_ctx* ctx, uint64_t* bad);
 
 /*
- * Adjoint of one step, for gradients through lbm_step (FP32 contexts only,
- * else LBM_ERR_UNSUPPORTED).  All pointers are device pointers to ten planes
+ * Adjoint of one step, for gradients through lbm_step (FP32 contexts without
+ * a body force only, else LBM_ERR_UNSUPPORTED).  All pointers are device pointers to ten planes
  * of nx*ny*nz floats:
  *   m_t      the raw FP32 state the step was taken from (the lbm_get_raw
  *            layout: plane 0 holds rho - 1);
@@ -276,8 +282,9 @@ int lbm_batch_create(int count, const int* dims, const double* taus, const uint8
 int lbm_batch_destroy(lbm_batch* b);
 const char* lbm_batch_last_error(const lbm_batch* b);
 int lbm_batch_set_stream(lbm_batch* b, void* hip_stream);
-/* dither_mode, seed and check_health as in lbm_options; inflow and tile_rows
- * must be 0 (LBM_ERR_UNSUPPORTED / LBM_ERR_INVALID_ARG otherwise). */
+/* dither_mode, seed and check_health as in lbm_options; inflow and force
+ * must be 0 (LBM_ERR_UNSUPPORTED otherwise) and tile_rows 0
+ * (LBM_ERR_INVALID_ARG otherwise). */
 int lbm_batch_set_options(lbm_batch* b, const lbm_options* opt);
 int lbm_batch_get_options(const lbm_batch* b, lbm_options* opt);
 /* dims of domain d, its first cell in the batch's planes and its cell count. */

@@ -193,6 +193,8 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   p.dither = mode != 0;
   p.key = dither_key(uint32_t(c->t), c->opt.seed, mode);
   for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
+  for (int a = 0; a < 3; ++a) p.hF[a] = 0.5f * c->opt.force[a];
+  p.force = (c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f) ? 1 : 0;
   if (c->n_fluid_b > 0) p.lc = ListedCells{c->d_lpack, c->d_side, uint32_t(c->n_fluid_b)};
   return p;
 }
@@ -343,6 +345,9 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
   if (o->tile_rows != 0 && std::find(std::begin(kFluidTileRows), std::end(kFluidTileRows), o->tile_rows) ==
                                std::end(kFluidTileRows))
     return fail(c, LBM_ERR_INVALID_ARG, "tile_rows must be 0, 8, 10, 12 or 13");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(o->force[a]) || std::fabs(o->force[a]) > 0.01f)
+      return fail(c, LBM_ERR_INVALID_ARG, "force must be finite with |F_a| <= 0.01");
   int r = check_faces(c, *o);
   if (r != LBM_OK) return r;
   if (o->inflow && c->d_mask) {
@@ -584,6 +589,8 @@ int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, 
 int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float* lam_prev) {
   if (!c || !m_t || !lam_next || !lam_prev) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
   if (c->fmt != FMT_F32) return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step needs FP32 moments");
+  if (c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f)
+    return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step has no body-force terms");
   if (static_cast<const void*>(lam_prev) == static_cast<const void*>(lam_next) ||
       static_cast<const void*>(lam_prev) == static_cast<const void*>(m_t))
     return fail(c, LBM_ERR_INVALID_ARG, "lam_prev must not alias lam_next or m_t");

@@ -79,14 +79,6 @@ __device__ inline CellIn load_cell_b(const StepParams& a, uint32_t cell) {
 }
 
 template <int FMT>
-__device__ inline void post_coeffs(const StepParams& a, uint32_t cell, float A[NA]) {
-  const CellIn c = load_cell_b<FMT>(a, cell);
-  float Nn[6];
-  collide_neq(c.N, a.om1, Nn);
-  hermite_coeffs(c.dr, c.j, c.u, Nn, A);
-}
-
-template <int FMT>
 __device__ inline void store_cell_b(const StepParams& a, uint32_t cell, float dr, const float j[3], const float P[6]) {
   const uint32_t off = cell * 4u;
   if constexpr (FMT == FMT_F32) {
@@ -115,17 +107,27 @@ __device__ inline void rest_words(uint32_t w[5]) {
 
 // Post-collision coefficients of cell q (with the inflow velocity when
 // `inflow`: rho^p = rho^q, u^p = u_in, the non-equilibrium stress of q).
+// With a body force, the non-equilibrium stress is that of the forced
+// collision and u^p stays u_in.
 template <int FMT>
 __device__ inline void source_coeffs(const StepParams& a, uint32_t q, bool inflow, float A[NA]) {
   const CellIn c = load_cell_b<FMT>(a, q);
-  float Nn[6];
-  collide_neq(c.N, a.om1, Nn);
-  if (inflow) {
-    const float jin[3] = {c.rho * a.u_in[0], c.rho * a.u_in[1], c.rho * a.u_in[2]};
-    hermite_coeffs(c.dr, jin, a.u_in, Nn, A);
-  } else {
-    hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+  if (!inflow) {
+    if (a.force)
+      post_collision<true>(c, a.om1, a.hF, A);
+    else
+      post_collision<false>(c, a.om1, a.hF, A);
+    return;
   }
+  float Nn[6];
+  if (a.force) {
+    float jp[3], up[3];
+    collide_force(c, a.hF, a.om1, jp, up, Nn);
+  } else {
+    collide_neq(c.N, a.om1, Nn);
+  }
+  const float jin[3] = {c.rho * a.u_in[0], c.rho * a.u_in[1], c.rho * a.u_in[2]};
+  hermite_coeffs(c.dr, jin, a.u_in, Nn, A);
 }
 
 // dm += (moments of link c) * df
@@ -149,19 +151,28 @@ __device__ inline void add_link(float m[10], int cx, int cy, int cz, float df) {
 // these codes at the start of every step (the boundary pass writes them, and
 // every way of setting the state keeps them), so the distribution the fluid
 // pass pulled from a solid neighbour is a constant of its direction.
+// With a body force the fluid pass collides the solid cells' rest state
+// with the force as well, and so does this.
 template <int FMT>
-__device__ inline void rest_coeffs(float om1, float A[NA]) {
+__device__ inline void rest_coeffs(const StepParams& a, float A[NA]) {
+  CellIn c;
   if constexpr (FMT == FMT_F32) {
+    if (!a.force) {
 #pragma unroll
-    for (int k = 0; k < NA; ++k) A[k] = 0.0f;
+      for (int k = 0; k < NA; ++k) A[k] = 0.0f;
+      return;
+    }
+    const float m[10] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    c = cell_from_moments(m);
   } else {
     uint32_t w[5];
     rest_words(w);
-    const CellIn c = cell_from_words(w);
-    float Nn[6];
-    collide_neq(c.N, om1, Nn);
-    hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+    c = cell_from_words(w);
   }
+  if (a.force)
+    post_collision<true>(c, a.om1, a.hF, A);
+  else
+    post_collision<false>(c, a.om1, a.hF, A);
 }
 
 // Listed fluid cell `cell` (list entry / side slot e, flags b, yz = y | z << 16).
@@ -189,7 +200,7 @@ __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t ce
   uint32_t bb = b & 0x7FFFFFFu & ~(1u << 13);
   if (bb) {
     float Arest[NA];
-    rest_coeffs<FMT>(a.om1, Arest);
+    rest_coeffs<FMT>(a, Arest);
     while (bb) {
       const int i = __ffs(bb) - 1;
       bb &= bb - 1u;

@@ -143,6 +143,39 @@ __device__ inline void collide_neq(const float N[6], float om1, float Nn[6]) {
   Nn[5] = om1 * N[5];
 }
 
+// App. A with a uniform body force F, written with h = F/2 and the
+// velocity u before the force (u = j / rho, j as stored, which by Eq.
+// rho_u_stress already holds the half force of the previous step):
+//   j+ = j + h,  u+ = j+ / rho,
+//   rho (S+ - u+ u+) = (1 - 1/tau) dev(N + h u + u h) - h h / rho.
+// Expanding App. A's forced off-diagonal and diagonal formulas around
+// u+ = u + h / rho gives these terms: the (2 tau - 1)/(2 tau rho) and
+// (tau - 1)/(3 tau rho) force terms combine into (1 - 1/tau) times the
+// deviatoric part of h u + u h, and u+ u+ leaves -h h / rho.
+__device__ inline void collide_force(const CellIn& c, const float h[3], float om1, float jp[3], float up[3],
+                                     float Nn[6]) {
+  const float Nf[6] = {fmaf(2.0f * h[0], c.u[0], c.N[0]),
+                       fmaf(2.0f * h[1], c.u[1], c.N[1]),
+                       fmaf(2.0f * h[2], c.u[2], c.N[2]),
+                       fmaf(h[0], c.u[1], fmaf(h[1], c.u[0], c.N[3])),
+                       fmaf(h[0], c.u[2], fmaf(h[2], c.u[0], c.N[4])),
+                       fmaf(h[1], c.u[2], fmaf(h[2], c.u[1], c.N[5]))};
+  collide_neq(Nf, om1, Nn);
+  const float inv = __builtin_amdgcn_rcpf(c.rho);
+  const float g[3] = {h[0] * inv, h[1] * inv, h[2] * inv};
+  Nn[0] = fmaf(-h[0], g[0], Nn[0]);
+  Nn[1] = fmaf(-h[1], g[1], Nn[1]);
+  Nn[2] = fmaf(-h[2], g[2], Nn[2]);
+  Nn[3] = fmaf(-h[0], g[1], Nn[3]);
+  Nn[4] = fmaf(-h[0], g[2], Nn[4]);
+  Nn[5] = fmaf(-h[1], g[2], Nn[5]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    jp[a] = c.j[a] + h[a];
+    up[a] = c.u[a] + g[a];
+  }
+}
+
 // Channel order of the 17 coefficients A_nml (n along x, m along y, l along z).
 enum {
   A000, A100, A010, A001, A200, A020, A002, A110, A101, A011,
@@ -185,6 +218,21 @@ __device__ inline void hermite_coeffs(float dr, const float j[3], const float u[
   A[A021] = fmaf(u[2], hyy, Nn[5] * u[1]);  // yyz
   A[A012] = fmaf(u[1], hzz, Nn[5] * u[2]);  // zzy
   A[A111] = fmaf(u[2], xy, fmaf(Nn[4], u[1], Nn[5] * u[0]));
+}
+
+// Post-collision coefficients of a decoded cell: App. A without force, or
+// with the body force h = F/2 (FORCE).
+template <bool FORCE>
+__device__ inline void post_collision(const CellIn& c, float om1, const float h[3], float A[NA]) {
+  float Nn[6];
+  if constexpr (FORCE) {
+    float jp[3], up[3];
+    collide_force(c, h, om1, jp, up, Nn);
+    hermite_coeffs(c.dr, jp, up, Nn, A);
+  } else {
+    collide_neq(c.N, om1, Nn);
+    hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+  }
 }
 
 // ------------------------------------------------- 1D reconstruct / project ---

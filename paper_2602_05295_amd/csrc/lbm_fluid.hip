@@ -120,7 +120,9 @@ __device__ inline void keep_listed(const ListedCells& lc, uint32_t cell, const L
 
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-template <int FMT, int TYR>
+// FORCE: App. A with the uniform body force a.hF = F/2 (collision terms, and
+// F/2 added to the projected momentum, Eq. rho_u_stress).
+template <int FMT, int TYR, bool FORCE>
 __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg) {
   constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
   __shared__ FluidLds<TYR> L;
@@ -198,10 +200,8 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
       if (p + 1 <= zb) nxt = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
 
       const CellIn c = decode<FMT>(cur);
-      float Nn[6];
-      collide_neq(c.N, a.om1, Nn);
       float A[NA];
-      hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+      post_collision<FORCE>(c, a.om1, a.hF, A);
 
       // ---- y pass: groups (n, l) with inputs m = 0, 1, 2 along y
       float f0[8], fp[8], fm[8];
@@ -288,6 +288,10 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
           sP[0] = proj1(w0[3], wp2[3], zfm[3]);             // Pxx
           sP[3] = proj1(w0[4], wp2[4], zfm[4]);             // Pxy
           sP[1] = proj1(w0[5], wp2[5], zfm[5]);             // Pyy
+          if constexpr (FORCE) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sj[k] += a.hF[k];
+          }
         }
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
@@ -347,20 +351,20 @@ int device_cus() {
   return cached[dev];
 }
 
-template <int FMT>
+template <int FMT, bool FORCE>
 hipError_t launch_rows(int rows, dim3 grid, const StepParams& p, int ntx, int nty, int nseg, int nwg, hipStream_t s) {
   switch (rows) {
     case 8:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 8>), grid, dim3(11 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE>), grid, dim3(11 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
     case 10:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 10>), grid, dim3(13 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE>), grid, dim3(13 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
     case 12:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 12>), grid, dim3(15 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE>), grid, dim3(15 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
     default:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 13>), grid, dim3(16 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE>), grid, dim3(16 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
   }
   return hipGetLastError();
@@ -410,8 +414,11 @@ hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {
   const FluidPlan c = fluid_plan(p.g, rows, device_cus());
   if (c.rows == 0) return hipErrorInvalidValue;
   const dim3 grid(uint32_t(c.nwg));
-  if (fmt == FMT_F32) return launch_rows<FMT_F32>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
-  return launch_rows<FMT_Q16>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  if (fmt == FMT_F32)
+    return p.force ? launch_rows<FMT_F32, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
+                   : launch_rows<FMT_F32, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  return p.force ? launch_rows<FMT_Q16, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
+                 : launch_rows<FMT_Q16, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
 }
 
 }  // namespace lbm

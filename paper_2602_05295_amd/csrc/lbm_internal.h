@@ -60,6 +60,8 @@ struct StepParams {
   uint32_t key;        // dither key of this step
   int dither;          // 0: round to nearest; else add the dither of `key`
   float u_in[3];
+  float hF[3];         // half the body force, F / 2 (App. A); zero without force
+  int force;           // hF != 0
   ListedCells lc;      // lc.side == nullptr: no listed cells
 };
 

@@ -37,6 +37,7 @@ class Options(ctypes.Structure):
         ("u_in", ctypes.c_float * 3),
         ("check_health", ctypes.c_int),
         ("tile_rows", ctypes.c_int),
+        ("force", ctypes.c_float * 3),
     ]
 
 
@@ -239,7 +240,8 @@ class HomeLBM:
         self._check(lib().lbm_get_options(self._h, ctypes.byref(o)))
         return o
 
-    def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None, tile_rows=None):
+    def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None, tile_rows=None,
+                    force=None):
         o = self.options()
         if dither_mode is not None:
             o.dither_mode = int(dither_mode)
@@ -253,6 +255,8 @@ class HomeLBM:
             o.check_health = int(bool(check_health))
         if tile_rows is not None:
             o.tile_rows = int(tile_rows)
+        if force is not None:
+            o.force = (ctypes.c_float * 3)(*[float(v) for v in force])
         self._check(lib().lbm_set_options(self._h, ctypes.byref(o)))
 
     def set_stream(self, stream):

@@ -25,7 +25,7 @@ def test_options_struct_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"(\w+)\s+(\w+)(\[\d+\])?;", body)
     assert [f[1] for f in fields] == [f[0] for f in homelbm.Options._fields_]
-    assert ctypes.sizeof(homelbm.Options) == 4 * 8
+    assert ctypes.sizeof(homelbm.Options) == 4 * 11
 
 
 def test_default_options_without_gpu():
@@ -77,3 +77,9 @@ def test_fluid_plan_host_logic():
     assert t["nwg"] == 1 and t["nseg"] == 1
     with pytest.raises(homelbm.LBMError):
         plan((8, 8, 8), tile_rows=7)
+
+
+def test_default_options_have_no_force():
+    o = homelbm.Options()
+    assert homelbm.lib().lbm_default_options(ctypes.byref(o)) == 0
+    assert list(o.force) == [0.0, 0.0, 0.0]

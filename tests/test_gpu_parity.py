@@ -28,8 +28,8 @@ def _note(*a):
     print("CASE", *a, flush=True)
 
 
-def _orc_params(orc, dims, tau, inflow=False, u_in=(0, 0, 0)):
-    return orc.make_params(dims, tau, inflow=inflow, u_in=u_in)
+def _orc_params(orc, dims, tau, inflow=False, u_in=(0, 0, 0), F=(0, 0, 0)):
+    return orc.make_params(dims, tau, F=F, inflow=inflow, u_in=u_in)
 
 
 def _faces_clear(mask):
@@ -154,17 +154,17 @@ def test_fp32_bitwise_reproducible(H):
 
 # ------------------------------------------------------------------- Q16 ---
 
-def _q16_step_compare(H, orc, dims, tau, mask=None, inflow=False, mode=1, seed=7, t0=3, steps=1):
+def _q16_step_compare(H, orc, dims, tau, mask=None, inflow=False, mode=1, seed=7, t0=3, steps=1, F=(0, 0, 0)):
     m = W.random_moments(*dims, seed=11, dj=0.02, dp=0.003)
     u_in = (0.05, 0.0, 0.01)
     with H.HomeLBM(dims, tau, mask=mask, fmt="q16") as s:
-        s.set_options(dither_mode=mode, seed=seed, inflow=inflow, u_in=u_in)
+        s.set_options(dither_mode=mode, seed=seed, inflow=inflow, u_in=u_in, force=F)
         s.set_moments(m.astype(np.float32))
         s.step_count = t0
         w0 = s.get_raw().copy()
         s.step(steps)
         got = s.get_raw()
-    P = _orc_params(orc, dims, tau, inflow, u_in)
+    P = _orc_params(orc, dims, tau, inflow, u_in, F)
     w = w0
     for k in range(steps):
         w = orc.q16_step(P, w, mask, t=t0 + k, seed=seed, mode=mode)
@@ -420,3 +420,106 @@ def test_step_into_matches_step(H, fmt, inflow):
         assert np.array_equal(own, want)  # the context's own state: still the state after its 5 steps
         with pytest.raises(H.LBMError):
             s.step_into(a, a)
+
+
+
+# ------------------------------------------------------------ body force ---
+# App. A with a uniform force F (the stored momentum holds F/2, Eq.
+# rho_u_stress).  The oracle applies App. A's printed formulas literally; the
+# kernels use their non-equilibrium form.
+
+FORCE = (2e-3, -1e-3, 5e-4)
+
+
+def _force_mask(dims, case, seed):
+    if case == "periodic":
+        return None, False
+    mask = W.sphere_mask(*dims, phi=0.08, rmin=1.5, rmax=3.0, seed=seed)
+    if case == "faces":
+        return _faces_clear(mask), True
+    return mask, False
+
+
+@pytest.mark.parametrize("case", ["periodic", "solids", "faces"])
+def test_fp32_body_force_steps(H, orc, case):
+    dims = (26, 19, 13)
+    _note("fp32 body force", case)
+    mask, inflow = _force_mask(dims, case, 5)
+    m = W.random_moments(*dims, seed=3).astype(np.float32)
+    u_in = (0.06, 0.01, -0.02)
+    with H.HomeLBM(dims, 0.62, mask=mask) as s:
+        s.set_options(inflow=inflow, u_in=u_in, force=FORCE)
+        s.set_moments(m)
+        m0 = s.get_moments()
+        s.step(5)
+        got = s.get_moments()
+    P = _orc_params(orc, dims, 0.62, inflow, u_in, FORCE)
+    ref = orc.run(P, m0.astype(np.float64), 5, mask)
+    err = group_rel_err(got, ref)
+    assert max(err.values()) <= TOL32, err
+    # the force is not a no-op at this tolerance
+    ref0 = orc.run(_orc_params(orc, dims, 0.62, inflow, u_in), m0.astype(np.float64), 5, mask)
+    assert max(group_rel_err(ref0, ref).values()) > 100 * TOL32
+
+
+@pytest.mark.parametrize("case", ["periodic", "solids", "faces"])
+def test_q16_body_force_one_step_codes(H, orc, case):
+    dims = (30, 21, 11)
+    _note("q16 body force", case)
+    mask, inflow = _force_mask(dims, case, 6)
+    got, ref = _q16_step_compare(H, orc, dims, 0.6, mask=mask, inflow=inflow, F=FORCE)
+    fl = np.ones(dims[::-1], bool) if mask is None else (mask == 0)
+    d = np.abs(unpack(got) - unpack(ref))[:, fl]
+    assert d.max() <= 1, d.max()
+    assert (d > 0).mean() < 0.01, (d > 0).mean()
+
+
+def test_body_force_rejected_where_unsupported(H):
+    with H.HomeLBM((8, 8, 8), 0.6) as s:
+        with pytest.raises(H.LBMError):
+            s.set_options(force=(0.02, 0.0, 0.0))  # |F_a| > 0.01
+        with pytest.raises(H.LBMError):
+            s.set_options(force=(float("nan"), 0.0, 0.0))
+        import torch
+        s.set_options(force=(1e-3, 0.0, 0.0))
+        m = torch.zeros((10, 8, 8, 8), device="cuda")
+        with pytest.raises(H.LBMError):
+            s.adjoint_step(m, m.clone(), m.clone())
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_poiseuille_with_body_force(H, orc, fmt):
+    """Force-driven channel between halfway bounce-back walls at y = 1/2 and
+    y = W + 1/2: the steady profile is u(y) = F/(2 rho nu) (y - 1/2)(W + 1/2 - y)
+    to within 2% (relative L2), and the FP32 run lands on the oracle's
+    steady state."""
+    Wd, F, tau = 16, 1e-5, 0.8
+    nx = nz = 4
+    ny = Wd + 2
+    dims = (nx, ny, nz)
+    _note("poiseuille", fmt)
+    nu = (tau - 0.5) / 3
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, Wd + 1, :] = 1
+    y = np.arange(ny)
+    prof = F / (2 * nu) * (y - 0.5) * (Wd + 0.5 - y)
+    prof[0] = prof[-1] = 0
+    u = np.zeros((3, nz, ny, nx), np.float32)
+    u[0] = prof[None, :, None]
+    rho = np.ones((nz, ny, nx), np.float32)
+    steps = 3000
+    with H.HomeLBM(dims, tau, mask=mask, fmt=fmt) as s:
+        s.set_options(force=(F, 0.0, 0.0))
+        s.set_equilibrium(rho, u)
+        m0 = s.get_moments()
+        s.step(steps)
+        m = s.get_moments()
+    ux = (m[1] / m[0])[:, 1:Wd + 1, :]
+    ref = prof[1:Wd + 1][None, :, None]
+    rel = np.linalg.norm((ux - ref).ravel()) / (np.linalg.norm(ref) * np.sqrt(nx * nz))
+    assert rel < 0.02, rel
+    if fmt == "fp32":
+        mo = orc.run(orc.make_params(dims, tau, F=(F, 0, 0)), m0.astype(np.float64), steps, mask)
+        uo = (mo[1] / mo[0])[:, 1:Wd + 1, :]
+        assert np.abs(ux - uo).max() <= 1e-4 * np.abs(uo).max()
