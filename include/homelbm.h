@@ -88,6 +88,19 @@ typedef struct lbm_options {
                          Eq. rho_u_stress).  Default 0; each |F_a| <= 0.01.  Not
                          supported by lbm_adjoint_step (LBM_ERR_UNSUPPORTED) nor by
                          batches (force must be 0 there). */
+  int wall_rule;      /* solid links: 0 (default) halfway bounce-back, f_i(x) = f+_opp(i)(x);
+                         1 the solid coupling of Sec. 3.2: f_i(x) reconstructed from
+                         rho^p = rho^x, u^p = V + W x (p - C) of the link's object (see
+                         lbm_set_object) at the link midpoint p = x - c_i/2, and
+                         S^p = u^p u^p + (S^x - u^x u^x) of x's post-collision moments.
+                         The reconstruction does not depend on where p lies on the link,
+                         so the no-slip point of a voxel wall is the solid node.  Not
+                         supported by lbm_adjoint_step nor by batches. */
+  int track_forces;   /* 1: every step adds the force and torque the fluid exerts on each
+                         object (momentum exchange over its links, -(f_i(x) + f+_opp(i)(x)) c_i
+                         per link, torque about the object's center) to sums read by
+                         lbm_get_object_forces; 0 (default): not computed.  Not supported
+                         by batches. */
 } lbm_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -97,10 +110,11 @@ int lbm_default_options(lbm_options* opt);
  * Creates a context for an nx*ny*nz grid (dims[0..2] = nx, ny, nz, each >= 1,
  * nx*ny*nz <= 2^30).  tau > 1/2 is the relaxation time of App. A (kinematic
  * viscosity nu = (tau - 1/2)/3).  solid_mask is a host array of nx*ny*nz bytes,
- * 0 = fluid, 1 = solid, or NULL for no solids; it is copied.  moment_format is
+ * 0 = fluid, 1..255 = solid, the value naming the object the cell belongs to
+ * (lbm_set_object), or NULL for no solids; it is copied.  moment_format is
  * an lbm_moment_format.  The state starts at rest (rho = 1, j = 0, P = 0).
  * On success *out receives the context; on failure *out is set to NULL.
- * Errors: LBM_ERR_INVALID_ARG (dims, tau, format, mask values other than 0/1),
+ * Errors: LBM_ERR_INVALID_ARG (dims, tau, format),
  * LBM_ERR_OUT_OF_MEMORY, LBM_ERR_DEVICE.
  */
 int lbm_create(const int dims[3], double tau, const uint8_t* solid_mask, int moment_format, lbm_ctx** out);
@@ -172,6 +186,27 @@ int lbm_set_raw(lbm_ctx* ctx, const void* in, size_t bytes, int on_device);
  * the recomputation of a checkpointed segment before its adjoint steps.
  */
 int lbm_step_into(lbm_ctx* ctx, const void* in, void* out);
+
+/*
+ * Motion of solid object id (1..255, the mask value of its cells) for wall
+ * rule 1, and the point torques are taken about: center C, velocity V and
+ * angular velocity W in lattice units (wall velocity V + W x (p - C), with p
+ * taken from the fluid cell's coordinates without periodic wrapping).  The
+ * cells do not move: this sets the velocity of the wall, as for a rotating
+ * cylinder or a sliding lid.  Every object starts at C = V = W = 0.  Ordered
+ * after the steps already enqueued; synchronises the context stream.
+ */
+int lbm_set_object(lbm_ctx* ctx, int id, const float center[3], const float velocity[3], const float omega[3]);
+
+/*
+ * Sums of the force and torque on every object over the steps since create
+ * or the last reset, computed while track_forces is set: out is a host array
+ * of 256 x 6 doubles, row id = (Fx, Fy, Fz, Tx, Ty, Tz), row 0 unused.
+ * reset = 1 zeroes the sums after reading them.  Synchronises the stream.
+ * The per-workgroup partial sums are added with atomics, so the last bits of
+ * the sums may differ from run to run.
+ */
+int lbm_get_object_forces(lbm_ctx* ctx, double* out, int reset);
 
 /* Step counter used by the dither. */
 int lbm_get_step_count(const lbm_ctx* ctx, uint64_t* t);

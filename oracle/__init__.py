@@ -47,14 +47,24 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double),
         ("F", ctypes.c_double * 3),
         ("u_in", ctypes.c_double * 3),
+        ("wall_rule", ctypes.c_int),
+        ("objects", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
-def make_params(dims, tau, F=(0.0, 0.0, 0.0), inflow=False, u_in=(0.0, 0.0, 0.0), literal_xyz=False) -> Params:
+def make_params(dims, tau, F=(0.0, 0.0, 0.0), inflow=False, u_in=(0.0, 0.0, 0.0), literal_xyz=False,
+                wall_rule=0, objects=None) -> Params:
+    """objects: None or a (256, 9) array, row id = center C, velocity V,
+    angular velocity W of the solid object with mask value id (R16, R17)."""
     nx, ny, nz = (int(d) for d in dims)
-    return Params(nx, ny, nz, int(bool(inflow)), int(bool(literal_xyz)), float(tau),
-                  (ctypes.c_double * 3)(*[float(v) for v in F]),
-                  (ctypes.c_double * 3)(*[float(v) for v in u_in]))
+    P = Params(nx, ny, nz, int(bool(inflow)), int(bool(literal_xyz)), float(tau),
+               (ctypes.c_double * 3)(*[float(v) for v in F]),
+               (ctypes.c_double * 3)(*[float(v) for v in u_in]), int(wall_rule), None)
+    if objects is not None:
+        obj = np.ascontiguousarray(objects, dtype=np.float64).reshape(256, 9)
+        P.object_table = obj  # keeps the table alive as long as the params
+        P.objects = obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return P
 
 
 _P = ctypes.POINTER
@@ -79,6 +89,7 @@ def lib():
         L.orc_collide.argtypes = [ctypes.c_double, _dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_post_collision_f.argtypes = [_P(Params), _dp, _dp, _dp, _dp]
         L.orc_step.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int]
+        L.orc_object_forces.argtypes = [_P(Params), _u8, _dp, _dp]
         L.orc_step_f32.argtypes = [_P(Params), _u8, _fp, _fp, ctypes.c_int]
         L.orc_step_cs.argtypes = [_P(Params), _u8, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.orc_step_cells.argtypes = [_P(Params), _u8, _dp, ctypes.c_int64, _i64, _dp, ctypes.c_int]
@@ -186,6 +197,15 @@ def step(params: Params, m, mask=None, nthreads=None):
     return out
 
 
+def object_forces(params: Params, m, mask):
+    """(256, 6) force and torque on each object id during the step from m (R17)."""
+    m = _check_field(m, params, np.float64)
+    out = np.zeros((256, 6), np.float64)
+    mk, mp = _mask_ptr(mask)
+    lib().orc_object_forces(ctypes.byref(params), mp, _ptr(m, _dp), _ptr(out, _dp))
+    return out
+
+
 def run(params: Params, m, nsteps, mask=None, nthreads=None):
     for _ in range(nsteps):
         m = step(params, m, mask, nthreads)
@@ -231,7 +251,8 @@ def adjoint_step(params: Params, m_t, lam_next, mask=None):
     lam_next = _check_field(lam_next, params)
     out = np.zeros_like(m_t)
     mk, mp = _mask_ptr(mask)
-    lib().orc_adjoint_step(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), _ptr(out, _dp), 1)
+    if lib().orc_adjoint_step(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), _ptr(out, _dp), 1) != 0:
+        raise ValueError("the oracle's adjoint follows bounce-back walls only (wall_rule 0)")
     return out
 
 

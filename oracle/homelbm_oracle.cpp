@@ -47,6 +47,17 @@
 //       The face rule is applied before the solid rule.
 //   R12 Body force: the stored momentum includes F/2 (Eq. rho_u_stress) and
 //       the collision follows App. A with its force terms.
+//   R16 Wall rule 1 (the solid coupling of Sec. 3.2 on a voxel mask): the
+//       link from fluid x to its solid source s = x - c_i meets the solid at
+//       the link midpoint p = x - c_i/2; f_i(x) = h_i(rho^p, u^p, S^p) with
+//       rho^p = rho^x, u^p = V + W x (p - C) of the object s belongs to (mask
+//       value = object id, positions taken from x without wrapping) and
+//       S^p = u^p u^p + (S^x - u^x u^x), x's post-collision moments.  Wall
+//       rule 0 is R10.
+//   R17 Force and torque on an object: momentum exchange over its links,
+//       -(f_i(x) + f+_opp(i)(x)) c_i per link and step (the momentum the
+//       link's outgoing and returning distributions deliver to the solid),
+//       torque (p - C) x that, summed over the object's links.
 
 #include <algorithm>
 #include <cmath>
@@ -202,6 +213,9 @@ struct OrcParams {
   double tau;
   double F[3];      // uniform body force
   double u_in[3];   // inflow velocity
+  int wall_rule;    // 0: halfway bounce-back (R10); 1: moment wall (R16)
+  const double* objects;  // 256 x 9: center C, velocity V, angular velocity W of
+                          // object id (mask value); NULL: all at rest at 0
 };
 
 }  // extern "C"
@@ -230,8 +244,25 @@ Cell<T> load_post(const OrcParams& P, const T* in, int64_t N, int64_t c) {
   return collide(to_cell(m), P.F, P.tau);
 }
 
+// Velocity of object `id` at the midpoint p of the link from (x, y, z) along
+// -c (R16): V + W x (p - C).
+inline void wall_velocity(const OrcParams& P, int id, int x, int y, int z, int cx, int cy, int cz, double u[3]) {
+  double C[3] = {0, 0, 0}, V[3] = {0, 0, 0}, W[3] = {0, 0, 0};
+  if (P.objects) {
+    for (int a = 0; a < 3; ++a) {
+      C[a] = P.objects[9 * id + a];
+      V[a] = P.objects[9 * id + 3 + a];
+      W[a] = P.objects[9 * id + 6 + a];
+    }
+  }
+  const double r[3] = {x - 0.5 * cx - C[0], y - 0.5 * cy - C[1], z - 0.5 * cz - C[2]};
+  u[0] = V[0] + W[1] * r[2] - W[2] * r[1];
+  u[1] = V[1] + W[2] * r[0] - W[0] * r[2];
+  u[2] = V[2] + W[0] * r[1] - W[1] * r[0];
+}
+
 // f_i arriving at fluid cell (x, y, z) after the pull-stream, with the face
-// and wall rules (R10, R11).  post(c) returns the post-collision Cell of c.
+// and wall rules (R10, R11, R16).  post(c) returns the post-collision Cell of c.
 template <class T, class PostFn>
 T pulled(const Grid<T>& G, int x, int y, int z, int i, PostFn&& post) {
   const OrcParams& P = G.P;
@@ -256,7 +287,19 @@ T pulled(const Grid<T>& G, int x, int y, int z, int i, PostFn&& post) {
   if (!P.inflow) sx = wrap(sx, P.nx);
   const int sy = wrap(y - cy, P.ny), sz = wrap(z - cz, P.nz);
   const int64_t s = G.idx(sx, sy, sz);
-  if (G.solid(s)) return hermite_f(LAT.opp[i], post(G.idx(x, y, z)), lit);
+  if (G.solid(s)) {
+    if (P.wall_rule == 0) return hermite_f(LAT.opp[i], post(G.idx(x, y, z)), lit);
+    // moment wall (R16): rho^p = rho^x, u^p of the object, S^p = u^p u^p + (S^x - u^x u^x)
+    const Cell<T> q = post(G.idx(x, y, z));
+    double up[3];
+    wall_velocity(P, G.mask[s], x, y, z, cx, cy, cz, up);
+    Cell<T> pc;
+    pc.rho = q.rho;
+    for (int a = 0; a < 3; ++a) pc.u[a] = T(up[a]);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) pc.S[a][b] = T(up[a] * up[b]) + (q.S[a][b] - q.u[a] * q.u[b]);
+    return hermite_f(i, pc, lit);
+  }
   return hermite_f(i, post(s), lit);
 }
 
@@ -470,6 +513,46 @@ int orc_step(const OrcParams* P, const uint8_t* mask, const double* in, double* 
   return 0;
 }
 
+// Force and torque on every object during the step from `in` (R17), summed
+// over the links of the fluid cells whose source is solid: out[6 id + 0..2]
+// force, out[6 id + 3..5] torque about the object's center, ids 0..255.
+int orc_object_forces(const OrcParams* P, const uint8_t* mask, const double* in, double* out) {
+  Grid<double> G(*P, mask);
+  const int64_t N = G.N;
+  for (int k = 0; k < 256 * 6; ++k) out[k] = 0.0;
+  if (!mask) return 0;
+  auto get = [&](int64_t c) { return load_post(*P, in, N, c); };
+  for (int z = 0; z < P->nz; ++z)
+    for (int y = 0; y < P->ny; ++y)
+      for (int x = 0; x < P->nx; ++x) {
+        const int64_t c = G.idx(x, y, z);
+        if (G.solid(c)) continue;
+        for (int i = 0; i < 27; ++i) {
+          const int cx = LAT.c[i][0], cy = LAT.c[i][1], cz = LAT.c[i][2];
+          if (P->inflow && ((x == 0 && cx == +1) || (x == P->nx - 1 && cx == -1))) continue;
+          int sx = x - cx;
+          if (!P->inflow) sx = wrap(sx, P->nx);
+          const int64_t s = G.idx(sx, wrap(y - cy, P->ny), wrap(z - cz, P->nz));
+          if (!G.solid(s)) continue;
+          const int id = mask[s];
+          const double f_in = pulled(G, x, y, z, i, get);
+          const double f_out = hermite_f(LAT.opp[i], get(c), P->literal_xyz != 0);
+          double dp[3];
+          for (int a = 0; a < 3; ++a) dp[a] = -(f_in + f_out) * LAT.cd[i][a];
+          double C[3] = {0, 0, 0};
+          if (P->objects)
+            for (int a = 0; a < 3; ++a) C[a] = P->objects[9 * id + a];
+          const double r[3] = {x - 0.5 * cx - C[0], y - 0.5 * cy - C[1], z - 0.5 * cz - C[2]};
+          double* o = out + 6 * id;
+          for (int a = 0; a < 3; ++a) o[a] += dp[a];
+          o[3] += r[1] * dp[2] - r[2] * dp[1];
+          o[4] += r[2] * dp[0] - r[0] * dp[2];
+          o[5] += r[0] * dp[1] - r[1] * dp[0];
+        }
+      }
+  return 0;
+}
+
 int orc_step_f32(const OrcParams* P, const uint8_t* mask, const float* in, float* out, int nthreads) {
   step_grid<float>(*P, mask, in, out, nthreads > 0 ? nthreads : 1);
   return 0;
@@ -582,6 +665,7 @@ int orc_q16_step_cells(const OrcParams* P, const uint8_t* mask, const uint32_t* 
 int orc_adjoint_step(const OrcParams* P, const uint8_t* mask, const double* m_t, const double* lam_next,
                      double* lam_prev, int nthreads) {
   (void)nthreads;
+  if (P->wall_rule != 0) return -1;  // the adjoint follows bounce-back walls only
   Grid<double> G(*P, mask);
   const int64_t N = G.N;
   const bool lit = P->literal_xyz != 0;

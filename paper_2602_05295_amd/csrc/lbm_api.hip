@@ -39,6 +39,9 @@ struct lbm_ctx {
   uint32_t* d_counters = nullptr;     // 3 list counters
   unsigned long long* d_bad = nullptr;
   uint8_t* d_flags = nullptr;         // adjoint cell flags (built on first use)
+  float h_objects[256 * 9] = {};      // per object id: center, velocity, angular velocity
+  float* d_objects = nullptr;         // device copy of h_objects
+  double* d_forces = nullptr;         // 256 x 6 force and torque sums (track_forces)
   bool flags_valid = false;
   bool list_built = false;
   int list_inflow = -1;
@@ -195,6 +198,10 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
   for (int a = 0; a < 3; ++a) p.hF[a] = 0.5f * c->opt.force[a];
   p.force = (c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f) ? 1 : 0;
+  p.wall_rule = c->opt.wall_rule;
+  p.mask = c->d_mask;
+  p.objects = c->d_objects;
+  p.forces = c->opt.track_forces ? c->d_forces : nullptr;
   if (c->n_fluid_b > 0) p.lc = ListedCells{c->d_lpack, c->d_side, uint32_t(c->n_fluid_b)};
   return p;
 }
@@ -270,12 +277,8 @@ int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_
   if (fmt != LBM_MOMENTS_FP32 && fmt != LBM_MOMENTS_Q16)
     return fail(nullptr, LBM_ERR_INVALID_ARG, "unknown moment format");
   bool any_solid = false;
-  if (mask) {
-    for (int64_t k = 0; k < N; ++k) {
-      if (mask[k] > 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "mask values must be 0 or 1");
-      any_solid = any_solid || mask[k];
-    }
-  }
+  if (mask)
+    for (int64_t k = 0; k < N && !any_solid; ++k) any_solid = mask[k] != 0;
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(nullptr, LBM_ERR_OUT_OF_MEMORY, "host allocation failed");
   c->nx = dims[0];
@@ -289,6 +292,10 @@ int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_
   for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], state_bytes(c));
   if (e == hipSuccess) e = hipMalloc(&c->d_counters, 4 * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&c->d_objects, sizeof(c->h_objects));
+  if (e == hipSuccess) e = hipMemcpy(c->d_objects, c->h_objects, sizeof(c->h_objects), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_forces, 256 * 6 * sizeof(double));
+  if (e == hipSuccess) e = hipMemset(c->d_forces, 0, 256 * 6 * sizeof(double));
   if (e == hipSuccess && any_solid) {
     e = hipMalloc(&c->d_mask, size_t(N));
     if (e == hipSuccess) e = hipMemcpy(c->d_mask, mask, size_t(N), hipMemcpyHostToDevice);
@@ -329,6 +336,8 @@ int lbm_destroy(lbm_ctx* c) {
   if (c->d_counters) (void)hipFree(c->d_counters);
   if (c->d_bad) (void)hipFree(c->d_bad);
   if (c->d_flags) (void)hipFree(c->d_flags);
+  if (c->d_objects) (void)hipFree(c->d_objects);
+  if (c->d_forces) (void)hipFree(c->d_forces);
   delete c;
   return LBM_OK;
 }
@@ -348,6 +357,8 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(o->force[a]) || std::fabs(o->force[a]) > 0.01f)
       return fail(c, LBM_ERR_INVALID_ARG, "force must be finite with |F_a| <= 0.01");
+  if (o->wall_rule != 0 && o->wall_rule != 1) return fail(c, LBM_ERR_INVALID_ARG, "wall_rule must be 0 or 1");
+  if (o->track_forces != 0 && o->track_forces != 1) return fail(c, LBM_ERR_INVALID_ARG, "track_forces must be 0 or 1");
   int r = check_faces(c, *o);
   if (r != LBM_OK) return r;
   if (o->inflow && c->d_mask) {
@@ -444,6 +455,39 @@ int lbm_step(lbm_ctx* c, int n) {
     if (r != LBM_OK) return r;
     if (bad) return fail(c, LBM_ERR_UNSTABLE, "state holds " + std::to_string(bad) + " non-finite or saturated values");
   }
+  return LBM_OK;
+}
+
+int lbm_set_object(lbm_ctx* c, int id, const float center[3], const float velocity[3], const float omega[3]) {
+  if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
+  if (id < 1 || id > 255) return fail(c, LBM_ERR_INVALID_ARG, "object ids are 1..255");
+  if (!center || !velocity || !omega) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(center[a]) || !std::isfinite(velocity[a]) || !std::isfinite(omega[a]))
+      return fail(c, LBM_ERR_INVALID_ARG, "object motion must be finite");
+  float* o = c->h_objects + 9 * id;
+  for (int a = 0; a < 3; ++a) {
+    o[a] = center[a];
+    o[3 + a] = velocity[a];
+    o[6 + a] = omega[a];
+  }
+  // ordered after earlier steps on the context stream
+  const hipError_t e = hipMemcpyAsync(c->d_objects + 9 * id, o, 9 * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    const hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (e2 != hipSuccess) return hip_fail(c, e2, "set_object");
+  } else {
+    return hip_fail(c, e, "set_object");
+  }
+  return LBM_OK;
+}
+
+int lbm_get_object_forces(lbm_ctx* c, double* out, int reset) {
+  if (!c || !out) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  hipError_t e = hipMemcpyAsync(out, c->d_forces, 256 * 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && reset) e = hipMemsetAsync(c->d_forces, 0, 256 * 6 * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "get_object_forces");
   return LBM_OK;
 }
 
@@ -591,6 +635,7 @@ int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float*
   if (c->fmt != FMT_F32) return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step needs FP32 moments");
   if (c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f)
     return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step has no body-force terms");
+  if (c->opt.wall_rule != 0) return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step follows bounce-back walls only");
   if (static_cast<const void*>(lam_prev) == static_cast<const void*>(lam_next) ||
       static_cast<const void*>(lam_prev) == static_cast<const void*>(m_t))
     return fail(c, LBM_ERR_INVALID_ARG, "lam_prev must not alias lam_next or m_t");

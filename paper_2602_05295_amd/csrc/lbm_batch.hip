@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(256) batch_boundary_fluid_kernel(BatchStepPara
   const int e = int(blockIdx.x) * 256 + int(threadIdx.x);
   if (e >= count) return;
   const StepParams p = domain_params<FMT>(a, a.doms[dom[e]]);
-  boundary_fix<FMT>(p, uint32_t(e), cells[e], bits[e], yz[e]);
+  boundary_fix<FMT, false>(p, uint32_t(e), cells[e], bits[e], yz[e], nullptr);
 }
 
 template <int FMT>

@@ -658,6 +658,8 @@ int lbm_batch_set_options(lbm_batch* b, const lbm_options* o) {
   if (o->inflow) return bfail(b, LBM_ERR_UNSUPPORTED, "batched domains are periodic (inflow must be 0)");
   if (o->force[0] != 0.0f || o->force[1] != 0.0f || o->force[2] != 0.0f)
     return bfail(b, LBM_ERR_UNSUPPORTED, "batched domains have no body force (force must be 0)");
+  if (o->wall_rule != 0 || o->track_forces != 0)
+    return bfail(b, LBM_ERR_UNSUPPORTED, "batched domains use bounce-back walls without force tracking");
   if (o->tile_rows != 0) return bfail(b, LBM_ERR_INVALID_ARG, "tile_rows must be 0 in a batch (see lbm_batch_set_tuning)");
   b->opt = *o;
   drop_graphs(b);

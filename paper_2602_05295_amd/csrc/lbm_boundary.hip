@@ -17,7 +17,28 @@ __global__ void __launch_bounds__(256) boundary_fluid_kernel(StepParams a, const
   const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
   if (t >= count) return;
   const uint32_t e = order ? order[t] : uint32_t(t);
-  boundary_fix<FMT>(a, e, cells[e], bits[e], yz[e]);
+  boundary_fix<FMT, false>(a, e, cells[e], bits[e], yz[e], nullptr);
+}
+
+// The same with the force and torque on each object summed (Sec. 3.2, last
+// step): per workgroup in LDS, then one double add per nonzero sum into
+// a.forces.
+template <int FMT>
+__global__ void __launch_bounds__(256) boundary_fluid_forces_kernel(StepParams a, const uint32_t* __restrict__ cells,
+                                                                    const uint32_t* __restrict__ bits,
+                                                                    const uint32_t* __restrict__ yz,
+                                                                    const uint32_t* __restrict__ order, int count) {
+  __shared__ float acc[256 * 6];
+  for (int k = int(threadIdx.x); k < 256 * 6; k += 256) acc[k] = 0.0f;
+  __syncthreads();
+  const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
+  if (t < count) {
+    const uint32_t e = order ? order[t] : uint32_t(t);
+    boundary_fix<FMT, true>(a, e, cells[e], bits[e], yz[e], acc);
+  }
+  __syncthreads();
+  for (int k = int(threadIdx.x); k < 256 * 6; k += 256)
+    if (acc[k] != 0.0f) atomicAdd(a.forces + k, double(acc[k]));
 }
 
 // Listed solid cells: one lane each.
@@ -33,10 +54,18 @@ hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, 
                            const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
   if (nfluid > 0) {
     const dim3 grid(uint32_t((nfluid + 255) / 256));
-    if (fmt == FMT_F32)
+    if (p.forces) {
+      if (fmt == FMT_F32)
+        hipLaunchKernelGGL(boundary_fluid_forces_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, order,
+                           nfluid);
+      else
+        hipLaunchKernelGGL(boundary_fluid_forces_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, order,
+                           nfluid);
+    } else if (fmt == FMT_F32) {
       hipLaunchKernelGGL(boundary_fluid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
-    else
+    } else {
       hipLaunchKernelGGL(boundary_fluid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

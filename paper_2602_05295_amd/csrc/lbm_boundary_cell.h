@@ -107,27 +107,63 @@ __device__ inline void rest_words(uint32_t w[5]) {
 
 // Post-collision coefficients of cell q (with the inflow velocity when
 // `inflow`: rho^p = rho^q, u^p = u_in, the non-equilibrium stress of q).
-// With a body force, the non-equilibrium stress is that of the forced
-// collision and u^p stays u_in.
+// Post-collision moments of a cell: rho - 1, rho, j+, u+ and the
+// non-equilibrium stress rho (S+ - u+ u+) (App. A, with the body force if any).
+struct PostCell {
+  float dr, rho, j[3], u[3], Nn[6];
+};
+
+template <int FMT>
+__device__ inline PostCell post_cell(const StepParams& a, uint32_t q) {
+  const CellIn c = load_cell_b<FMT>(a, q);
+  PostCell s;
+  s.dr = c.dr;
+  s.rho = c.rho;
+  if (a.force) {
+    collide_force(c, a.hF, a.om1, s.j, s.u, s.Nn);
+  } else {
+    collide_neq(c.N, a.om1, s.Nn);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.j[k] = c.j[k];
+      s.u[k] = c.u[k];
+    }
+  }
+  return s;
+}
+
+// Coefficients of the moments (rho^p = rho^x, u^p, S^p = u^p u^p + (S^x -
+// u^x u^x)) that Sec. 3.2 reconstructs at a boundary point p next to x: the
+// inflow face (u^p = u_in) and the moment wall (u^p of the solid).
+__device__ inline void boundary_point_coeffs(const PostCell& x, const float up[3], float A[NA]) {
+  const float jp[3] = {x.rho * up[0], x.rho * up[1], x.rho * up[2]};
+  hermite_coeffs(x.dr, jp, up, x.Nn, A);
+}
+
+// Post-collision coefficients of cell q (with the inflow velocity when
+// `inflow`: rho^p = rho^q, u^p = u_in, the non-equilibrium stress of q).
 template <int FMT>
 __device__ inline void source_coeffs(const StepParams& a, uint32_t q, bool inflow, float A[NA]) {
-  const CellIn c = load_cell_b<FMT>(a, q);
-  if (!inflow) {
-    if (a.force)
-      post_collision<true>(c, a.om1, a.hF, A);
-    else
-      post_collision<false>(c, a.om1, a.hF, A);
-    return;
-  }
-  float Nn[6];
-  if (a.force) {
-    float jp[3], up[3];
-    collide_force(c, a.hF, a.om1, jp, up, Nn);
-  } else {
-    collide_neq(c.N, a.om1, Nn);
-  }
-  const float jin[3] = {c.rho * a.u_in[0], c.rho * a.u_in[1], c.rho * a.u_in[2]};
-  hermite_coeffs(c.dr, jin, a.u_in, Nn, A);
+  const PostCell s = post_cell<FMT>(a, q);
+  if (inflow)
+    boundary_point_coeffs(s, a.u_in, A);
+  else
+    hermite_coeffs(s.dr, s.j, s.u, s.Nn, A);
+}
+
+// Velocity of object id at the midpoint p = x - c/2 of the link from cell
+// (x, y, z) along -c: V + W x (p - C), positions taken from the fluid cell
+// without wrapping.
+__device__ inline void wall_velocity(const float* obj, int x, int y, int z, int cx, int cy, int cz, float u[3],
+                                     float r[3]) {
+  r[0] = float(x) - 0.5f * float(cx) - obj[0];
+  r[1] = float(y) - 0.5f * float(cy) - obj[1];
+  r[2] = float(z) - 0.5f * float(cz) - obj[2];
+  const float* V = obj + 3;
+  const float* W = obj + 6;
+  u[0] = V[0] + (W[1] * r[2] - W[2] * r[1]);
+  u[1] = V[1] + (W[2] * r[0] - W[0] * r[2]);
+  u[2] = V[2] + (W[0] * r[1] - W[1] * r[0]);
 }
 
 // dm += (moments of link c) * df
@@ -189,23 +225,62 @@ __device__ inline void rest_coeffs(const StepParams& a, float A[NA]) {
 // Bounce-back links are walked per lane (a bit scan); face links, the same
 // nine for every face cell, in lockstep so that neighbouring face cells'
 // loads coalesce.
-template <int FMT>
-__device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t cell, uint32_t b, uint32_t yz) {
+//   - with wall rule 1 a solid link's new f+ is instead reconstructed at the
+//     link midpoint from (rho^x, u^p of the object, S^p) (Sec. 3.2);
+//   - TRACK: each solid link adds the momentum -(f_i(x) + f+_opp(i)(x)) c_i
+//     it delivers to its object, and the torque of that about the object's
+//     center, to acc (256 x 6, the workgroup's sums in LDS).
+template <int FMT, bool TRACK>
+__device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t cell, uint32_t b, uint32_t yz,
+                                    float* acc) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int y = int(yz & 0xFFFFu), z = int(yz >> 16);
   float m[10];
   side_load(a.lc.side, e, m);
+  const PostCell own = post_cell<FMT>(a, cell);
   float Aown[NA];
-  source_coeffs<FMT>(a, cell, false, Aown);
+  hermite_coeffs(own.dr, own.j, own.u, own.Nn, Aown);
   uint32_t bb = b & 0x7FFFFFFu & ~(1u << 13);
   if (bb) {
     float Arest[NA];
     rest_coeffs<FMT>(a, Arest);
+    const int x = int(cell - uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z)));
     while (bb) {
       const int i = __ffs(bb) - 1;
       bb &= bb - 1u;
       const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-      add_link(m, cx, cy, cz, eval_link(Aown, -cx, -cy, -cz) - eval_link(Arest, cx, cy, cz));
+      const float fout = eval_link(Aown, -cx, -cy, -cz);  // f+_opp(i)(x) - w_i
+      float fnew = fout;                                   // bounce-back
+      int id = 0;
+      float r[3] = {0.0f, 0.0f, 0.0f};
+      if (a.wall_rule != 0 || TRACK) {
+        const uint32_t s = uint32_t(wrap_step(x, -cx, nx)) +
+                           uint32_t(nx) * (uint32_t(wrap_step(y, -cy, ny)) + uint32_t(ny) * uint32_t(wrap_step(z, -cz, nz)));
+        id = a.mask[s];
+        float up[3];
+        wall_velocity(a.objects + 9 * id, x, y, z, cx, cy, cz, up, r);
+        if (a.wall_rule != 0) {
+          float Ap[NA];
+          boundary_point_coeffs(own, up, Ap);
+          fnew = eval_link(Ap, cx, cy, cz);
+        }
+      }
+      add_link(m, cx, cy, cz, fnew - eval_link(Arest, cx, cy, cz));
+      if constexpr (TRACK) {
+        float px[3], py[3], pz[3];
+        basis1(cx, px);
+        basis1(cy, py);
+        basis1(cz, pz);
+        const float g = -((fnew + fout) + 2.0f * (px[0] * py[0] * pz[0]));  // -(f_i + f+_opp(i)), w_i = w1 w1 w1
+        const float dp[3] = {g * float(cx), g * float(cy), g * float(cz)};
+        float* o = acc + 6 * id;
+        atomicAdd(o + 0, dp[0]);
+        atomicAdd(o + 1, dp[1]);
+        atomicAdd(o + 2, dp[2]);
+        atomicAdd(o + 3, r[1] * dp[2] - r[2] * dp[1]);
+        atomicAdd(o + 4, r[2] * dp[0] - r[0] * dp[2]);
+        atomicAdd(o + 5, r[0] * dp[1] - r[1] * dp[0]);
+      }
     }
   }
   if (b & (BIT_INFLOW | BIT_OUTFLOW)) {

@@ -62,6 +62,10 @@ struct StepParams {
   float u_in[3];
   float hF[3];         // half the body force, F / 2 (App. A); zero without force
   int force;           // hF != 0
+  int wall_rule;       // 0: halfway bounce-back; 1: the moment wall of Sec. 3.2
+  const uint8_t* mask;   // solid mask, value = object id (read by the wall rules)
+  const float* objects;  // 256 x 9 per object id: center C, velocity V, angular velocity W
+  double* forces;        // 256 x 6 sums of force and torque per object id, or nullptr
   ListedCells lc;      // lc.side == nullptr: no listed cells
 };
 

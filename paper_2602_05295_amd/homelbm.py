@@ -38,6 +38,8 @@ class Options(ctypes.Structure):
         ("check_health", ctypes.c_int),
         ("tile_rows", ctypes.c_int),
         ("force", ctypes.c_float * 3),
+        ("wall_rule", ctypes.c_int),
+        ("track_forces", ctypes.c_int),
     ]
 
 
@@ -90,6 +92,8 @@ def lib():
     L.lbm_set_equilibrium.argtypes = [vp, vp, vp, i]
     L.lbm_step.argtypes = [vp, i]
     L.lbm_step_into.argtypes = [vp, vp, vp]
+    L.lbm_set_object.argtypes = [vp, i, vp, vp, vp]
+    L.lbm_get_object_forces.argtypes = [vp, vp, i]
     L.lbm_get_moments.argtypes = [vp, vp, i]
     L.lbm_raw_bytes.argtypes = [vp]
     L.lbm_raw_bytes.restype = sz
@@ -241,7 +245,7 @@ class HomeLBM:
         return o
 
     def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None, tile_rows=None,
-                    force=None):
+                    force=None, wall_rule=None, track_forces=None):
         o = self.options()
         if dither_mode is not None:
             o.dither_mode = int(dither_mode)
@@ -257,7 +261,22 @@ class HomeLBM:
             o.tile_rows = int(tile_rows)
         if force is not None:
             o.force = (ctypes.c_float * 3)(*[float(v) for v in force])
+        if wall_rule is not None:
+            o.wall_rule = int(wall_rule)
+        if track_forces is not None:
+            o.track_forces = int(bool(track_forces))
         self._check(lib().lbm_set_options(self._h, ctypes.byref(o)))
+
+    def set_object(self, oid, center=(0.0, 0.0, 0.0), velocity=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0)):
+        """Wall motion of solid object oid (its mask value) and its torque center."""
+        f3 = lambda v: (ctypes.c_float * 3)(*[float(x) for x in v])
+        self._check(lib().lbm_set_object(self._h, int(oid), f3(center), f3(velocity), f3(omega)))
+
+    def object_forces(self, reset=False):
+        """(256, 6) sums of force and torque per object id since the last reset."""
+        out = np.zeros((256, 6), np.float64)
+        self._check(lib().lbm_get_object_forces(self._h, out.ctypes.data_as(ctypes.c_void_p), int(bool(reset))))
+        return out
 
     def set_stream(self, stream):
         self._check(lib().lbm_set_stream(self._h, ctypes.c_void_p(stream or 0)))

@@ -321,8 +321,10 @@ def test_invalid_arguments(H):
     assert e.value.status == H.ERR_INVALID_ARG
     with pytest.raises(H.LBMError):
         H.HomeLBM((4, 4, 4), 0.5)
-    with pytest.raises(H.LBMError):
-        H.HomeLBM((4, 4, 4), 0.6, mask=np.full(64, 2, np.uint8))
+    ids = np.zeros(64, np.uint8)
+    ids[21] = 2  # mask values 1..255 name solid objects
+    with H.HomeLBM((4, 4, 4), 0.6, mask=ids) as s:
+        assert s.boundary_counts()[1] == 1
     with pytest.raises(H.LBMError):
         H.HomeLBM((1 << 11, 1 << 10, 1 << 10), 0.6)
     mask = np.zeros((4, 4, 10), np.uint8)

@@ -213,3 +213,86 @@ def test_float_instantiation_floor(orc):
     for g in (slice(0, 1), slice(1, 4), slice(4, 10)):
         err = np.abs(m32[g] - m[g]).max() / np.abs(m[g]).max()
         assert err < 1e-4, (g, err)
+
+
+# ------------------------------------------- moment wall and wall forces ---
+# R16: the solid coupling of Sec. 3.2 (f_i(x) = h_i(rho^x, u^p, S^p)); its
+# distribution does not depend on where along the link p lies, so on a voxel
+# mask the no-slip point sits at the solid node: plane Couette flow between
+# walls at y = 0 and y = W + 1 is exactly linear.  R17: momentum exchange.
+
+def _channel(orc, rule, F=0.0, U=0.0, tau=0.8, Wd=16, steps=4000):
+    nx = nz = 4
+    ny = Wd + 2
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[:, 0, :] = 1
+    mask[:, Wd + 1, :] = 2
+    obj = np.zeros((256, 9))
+    obj[2, 3] = U
+    obj[1, :3] = obj[2, :3] = ((nx - 1) / 2, (Wd + 1) / 2, (nz - 1) / 2)
+    P = orc.make_params((nx, ny, nz), tau, F=(F, 0, 0), wall_rule=rule, objects=obj)
+    m = orc.equilibrium_moments(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    m = orc.run(P, m, steps, mask, nthreads=1)
+    return m, orc.object_forces(P, m, mask), (nx, ny, nz, Wd, (tau - 0.5) / 3)
+
+
+def test_moment_wall_couette_is_exactly_linear(orc):
+    U = 0.01
+    m, fo, (nx, ny, nz, Wd, nu) = _channel(orc, 1, U=U)
+    y = np.arange(1, Wd + 1)
+    ux = (m[1] / m[0])[:, 1:Wd + 1, :]
+    ref = (U * y / (Wd + 1))[None, :, None]
+    assert np.abs(ux - ref).max() < 1e-5 * U
+    # wall shear: the fluid pushes the still wall along +x and holds the moving one back
+    sig = nu * U / (Wd + 1) * nx * nz
+    assert abs(fo[1, 0] / sig - 1) < 1e-4 and abs(fo[2, 0] / sig + 1) < 1e-4
+    # torque about the channel's center: the shear couple, counter-clockwise about z
+    tz = fo[1, 5] + fo[2, 5]
+    assert 0.85 * Wd * sig < tz < 1.05 * Wd * sig
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_wall_forces_balance_the_body_force(orc, rule):
+    """At steady state every unit of momentum the body force puts into the
+    fluid goes into the walls: sum of F_x over objects = F x (fluid cells)."""
+    F = 1e-5
+    m, fo, (nx, ny, nz, Wd, nu) = _channel(orc, rule, F=F, steps=6000)
+    assert abs((fo[1, 0] + fo[2, 0]) / (F * nx * nz * Wd) - 1) < 1e-6
+    assert abs(fo[1, 1] + fo[2, 1]) < 1e-9 * abs(fo[1, 1])  # wall pressures cancel
+
+
+def test_moment_wall_keeps_rest(orc):
+    dims = (12, 10, 9)
+    mask = W.sphere_mask(*dims, phi=0.1, rmin=1.5, rmax=3.0, seed=2)
+    m = orc.equilibrium_moments(np.ones(dims[::-1]), np.zeros((3,) + dims[::-1]))
+    P = orc.make_params(dims, 0.7, wall_rule=1)
+    out = orc.run(P, m, 3, mask)
+    fl = mask == 0
+    assert np.abs(out[:, fl] - m[:, fl]).max() < 1e-15
+
+
+def test_torque_moves_with_the_center(orc):
+    """tau about C2 = tau about C1 + (C1 - C2) x F, for moving objects in a
+    random state: the torque is taken about the object's center."""
+    dims = (14, 12, 10)
+    mask = W.sphere_mask(*dims, phi=0.12, rmin=1.5, rmax=3.0, seed=4).astype(np.uint8)
+    rng = np.random.default_rng(0)
+    mask[mask > 0] = 1
+    mask[:, :, :6][mask[:, :, :6] > 0] = 7  # a second object
+    m = W.random_moments(*dims, seed=9, dj=0.02, dp=0.003).astype(np.float64)
+    obj1 = np.zeros((256, 9))
+    obj1[:, :3] = rng.uniform(0, 10, (256, 3))
+    obj1[:, 3:] = rng.uniform(-0.02, 0.02, (256, 6))
+    obj2 = obj1.copy()
+    obj2[:, :3] = rng.uniform(0, 10, (256, 3))
+    P1 = orc.make_params(dims, 0.7, wall_rule=1, objects=obj1)
+    f1 = orc.object_forces(P1, m, mask)
+    # the wall velocity changes with the center: keep u^p by moving V with it
+    obj2[:, 3:6] = obj1[:, 3:6] + np.cross(obj1[:, 6:], obj2[:, :3] - obj1[:, :3])
+    P2 = orc.make_params(dims, 0.7, wall_rule=1, objects=obj2)
+    f2 = orc.object_forces(P2, m, mask)
+    for k in (1, 7):
+        assert np.abs(f1[k, :3]).max() > 0
+        np.testing.assert_allclose(f2[k, :3], f1[k, :3], rtol=1e-12, atol=1e-15)
+        want = f1[k, 3:] + np.cross(obj1[k, :3] - obj2[k, :3], f1[k, :3])
+        np.testing.assert_allclose(f2[k, 3:], want, rtol=1e-10, atol=1e-13)
