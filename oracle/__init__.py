@@ -90,6 +90,12 @@ def lib():
         L.orc_post_collision_f.argtypes = [_P(Params), _dp, _dp, _dp, _dp]
         L.orc_step.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int]
         L.orc_object_forces.argtypes = [_P(Params), _u8, _dp, _dp]
+        L.orc_qb_encode.argtypes = [_dp, _u8, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, _u32]
+        L.orc_qb_decode.argtypes = [_u32, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _dp]
+        L.orc_qb_pack.argtypes = [_u32, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _u32]
+        L.orc_qb_step.argtypes = [_P(Params), _u8, _u32, _u32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_step_f32.argtypes = [_P(Params), _u8, _fp, _fp, ctypes.c_int]
         L.orc_step_cs.argtypes = [_P(Params), _u8, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.orc_step_cells.argtypes = [_P(Params), _u8, _dp, ctypes.c_int64, _i64, _dp, ctypes.c_int]
@@ -304,6 +310,50 @@ def q16_encode(m, mask=None, t=0, seed=0, mode=0):
     out = np.zeros((5,) + m.shape[1:], dtype=np.uint32)
     mk, mp = _mask_ptr(mask)
     lib().orc_q16_encode(_ptr(m, _dp), mp, N, t, seed, mode, _ptr(out, _u32))
+    return out
+
+
+def qb_words(b1, b2):
+    return (4 * b1 + 6 * b2 + 31) // 32
+
+
+def qb_encode(m, b1, b2, mask=None, t=0, seed=0, mode=0):
+    """Packed b1 / b2 codes (R18) of a (10, nz, ny, nx) field: (W, nz, ny, nx) words."""
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    N = int(np.prod(m.shape[1:]))
+    out = np.zeros((qb_words(b1, b2),) + m.shape[1:], dtype=np.uint32)
+    mk, mp = _mask_ptr(mask)
+    if lib().orc_qb_encode(_ptr(m, _dp), mp, N, t, seed, mode, b1, b2, _ptr(out, _u32)) != 0:
+        raise ValueError("bit widths must be 2..16")
+    return out
+
+
+def qb_decode(w, b1, b2):
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    N = int(np.prod(w.shape[1:]))
+    out = np.zeros((10,) + w.shape[1:])
+    if lib().orc_qb_decode(_ptr(w, _u32), N, b1, b2, _ptr(out, _dp)) != 0:
+        raise ValueError("bit widths must be 2..16")
+    return out
+
+
+def qb_pack(q, b1, b2):
+    """(10, ...) integer codes -> (W, ...) packed words."""
+    q = np.ascontiguousarray(q, dtype=np.uint32)
+    N = int(np.prod(q.shape[1:]))
+    out = np.zeros((qb_words(b1, b2),) + q.shape[1:], dtype=np.uint32)
+    lib().orc_qb_pack(_ptr(q, _u32), N, b1, b2, _ptr(out, _u32))
+    return out
+
+
+def qb_step(params: Params, w, b1, b2, mask=None, t=0, seed=0, mode=1, nthreads=None):
+    """decode -> FP64 step -> encode with the dither of step t, b1 / b2 codes."""
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    out = np.empty_like(w)
+    mk, mp = _mask_ptr(mask)
+    if lib().orc_qb_step(ctypes.byref(params), mp, _ptr(w, _u32), _ptr(out, _u32), t, seed, mode, b1, b2,
+                         nthreads or default_threads()) != 0:
+        raise ValueError("bit widths must be 2..16")
     return out
 
 

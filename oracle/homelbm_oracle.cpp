@@ -54,6 +54,10 @@
 //       value = object id, positions taken from x without wrapping) and
 //       S^p = u^p u^p + (S^x - u^x u^x), x's post-collision moments.  Wall
 //       rule 0 is R10.
+//   R18 Bit allocation b_rho_u / b_S: the codes of rho and u take b1 bits,
+//       those of N b2 bits (same ranges, rounding and dither), concatenated
+//       low bit first, rho, ux, uy, uz, Nxx, Nyy, Nzz, Nxy, Nxz, Nyz, into
+//       ceil((4 b1 + 6 b2)/32) words; 16/16 is the paired layout above.
 //   R17 Force and torque on an object: momentum exchange over its links,
 //       -(f_i(x) + f+_opp(i)(x)) c_i per link and step (the momentum the
 //       link's outgoing and returning distributions deliver to the solid),
@@ -445,6 +449,71 @@ void decode_cell(const uint32_t w[5], double m[10]) {
   codec_vars_to_moments(v, m);
 }
 
+// ---- b_rho_u / b_S bit allocation (the study of the double-layer vortex,
+// Sec. 6): b1 bits for rho and u, b2 bits for N, the same ranges, rounding
+// and dither, and the ten codes concatenated low bit first into
+// ceil((4 b1 + 6 b2) / 32) words (R18).  16/16 is the layout above.
+struct Bits {
+  int b1, b2;
+  int of(int k) const { return k < 4 ? b1 : b2; }
+  int words() const { return (4 * b1 + 6 * b2 + 31) / 32; }
+};
+
+uint32_t encode_one_b(double m, int k, double xi, int b) {
+  const uint32_t qmax = (1u << b) - 1u;
+  const float mf = float(m);
+  const float lo = float(Q_LO[k]);
+  const float scale = float(double(qmax) / (Q_HI[k] - Q_LO[k]));
+  const float v = (mf - lo) * scale + float(0.5 + xi);
+  if (!(v >= 0.0f)) return 0;
+  const float fl = std::floor(v);
+  if (fl >= float(qmax)) return qmax;
+  return uint32_t(fl);
+}
+
+double decode_one_b(uint32_t q, int k, int b) {
+  return Q_LO[k] + double(q) * ((Q_HI[k] - Q_LO[k]) / double((1u << b) - 1u));
+}
+
+// Stream bit o of a cell is bit o % 32 of its word o / 32; code k occupies
+// stream bits [o_k, o_k + b_k), o_k the sum of the widths before it.
+void pack_bits(const uint32_t q[10], const Bits& B, uint32_t* w) {
+  for (int i = 0; i < B.words(); ++i) w[i] = 0u;
+  int o = 0;
+  for (int k = 0; k < 10; ++k) {
+    for (int t = 0; t < B.of(k); ++t) w[(o + t) / 32] |= ((q[k] >> t) & 1u) << ((o + t) % 32);
+    o += B.of(k);
+  }
+}
+
+void unpack_bits(const uint32_t* w, const Bits& B, uint32_t q[10]) {
+  int o = 0;
+  for (int k = 0; k < 10; ++k) {
+    q[k] = 0u;
+    for (int t = 0; t < B.of(k); ++t) q[k] |= ((w[(o + t) / 32] >> ((o + t) % 32)) & 1u) << t;
+    o += B.of(k);
+  }
+}
+
+void encode_cell_b(const double m[10], uint32_t idx, uint32_t t, uint32_t seed, int mode, const Bits& B,
+                   uint32_t* w) {
+  double v[10], xi[10];
+  uint32_t h[2];
+  moments_to_codec_vars(m, v);
+  dither(idx, t, seed, mode, xi, h);
+  uint32_t q[10];
+  for (int k = 0; k < 10; ++k) q[k] = encode_one_b(v[k], k, xi[k], B.of(k));
+  pack_bits(q, B, w);
+}
+
+void decode_cell_b(const uint32_t* w, const Bits& B, double m[10]) {
+  uint32_t q[10];
+  unpack_bits(w, B, q);
+  double v[10];
+  for (int k = 0; k < 10; ++k) v[k] = decode_one_b(q[k], k, B.of(k));
+  codec_vars_to_moments(v, m);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint of one step, lam_prev = J(m_t)^T lam_next.  The per-cell Jacobians
 // of f+ (and of the inflow distributions) are taken by complex step of the
@@ -624,6 +693,57 @@ void orc_q16_decode(const uint32_t* w, int64_t N, double* m) {
     decode_cell(wc, mc);
     for (int k = 0; k < 10; ++k) m[k * N + c] = mc[k];
   }
+}
+
+// Packed codes with b1 / b2 bits (R18): words() planes of N words.
+int orc_qb_encode(const double* m, const uint8_t* mask, int64_t N, uint32_t t, uint32_t seed, int mode, int b1, int b2,
+                  uint32_t* w) {
+  const Bits B{b1, b2};
+  if (b1 < 2 || b1 > 16 || b2 < 2 || b2 > 16) return -1;
+  for (int64_t c = 0; c < N; ++c) {
+    double mc[10] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const bool sol = mask && mask[c];
+    if (!sol)
+      for (int k = 0; k < 10; ++k) mc[k] = m[k * N + c];
+    uint32_t wc[5];
+    encode_cell_b(mc, uint32_t(c), t, seed, sol ? 0 : mode, B, wc);
+    for (int p = 0; p < B.words(); ++p) w[p * N + c] = wc[p];
+  }
+  return 0;
+}
+
+int orc_qb_decode(const uint32_t* w, int64_t N, int b1, int b2, double* m) {
+  const Bits B{b1, b2};
+  if (b1 < 2 || b1 > 16 || b2 < 2 || b2 > 16) return -1;
+  for (int64_t c = 0; c < N; ++c) {
+    uint32_t wc[5];
+    for (int p = 0; p < B.words(); ++p) wc[p] = w[p * N + c];
+    double mc[10];
+    decode_cell_b(wc, B, mc);
+    for (int k = 0; k < 10; ++k) m[k * N + c] = mc[k];
+  }
+  return 0;
+}
+
+// Codes <-> packed words only (for pins of the layout): q is 10 x N.
+int orc_qb_pack(const uint32_t* q, int64_t N, int b1, int b2, uint32_t* w) {
+  const Bits B{b1, b2};
+  for (int64_t c = 0; c < N; ++c) {
+    uint32_t qc[10], wc[5];
+    for (int k = 0; k < 10; ++k) qc[k] = q[k * N + c];
+    pack_bits(qc, B, wc);
+    for (int p = 0; p < B.words(); ++p) w[p * N + c] = wc[p];
+  }
+  return 0;
+}
+
+int orc_qb_step(const OrcParams* P, const uint8_t* mask, const uint32_t* in, uint32_t* out, uint32_t t, uint32_t seed,
+                int mode, int b1, int b2, int nthreads) {
+  const int64_t N = int64_t(P->nx) * P->ny * P->nz;
+  std::vector<double> m(10 * N), m2(10 * N);
+  if (orc_qb_decode(in, N, b1, b2, m.data()) != 0) return -1;
+  step_grid<double>(*P, mask, m.data(), m2.data(), nthreads > 0 ? nthreads : 1);
+  return orc_qb_encode(m2.data(), mask, N, t, seed, mode, b1, b2, out);
 }
 
 // One 16-bit step: decode -> FP64 step -> encode with the dither of step t.

@@ -170,3 +170,83 @@ def test_q16_step_cells_matches_full(orc):
     cells = np.arange(np.prod(n))[1::4]
     part = orc.q16_step_cells(P, w, cells, mask, t=11, seed=4, mode=1)
     assert np.all(part == full.reshape(5, -1)[:, cells].T)
+
+
+# ------------------------------------------- b_rho_u / b_S allocation (R18) ---
+CONFIGS = [(16, 16), (16, 15), (15, 14), (14, 13), (13, 12), (12, 11)]
+
+
+def _unpack_stream(w, b1, b2):
+    """The ten codes of each cell, read back by treating its words as one
+    little-endian integer (word i = bits 32 i .. 32 i + 31)."""
+    W = w.shape[0]
+    flat = w.reshape(W, -1)
+    out = np.zeros((10, flat.shape[1]), np.int64)
+    for c in range(flat.shape[1]):
+        s = 0
+        for i in range(W):
+            s |= int(flat[i, c]) << (32 * i)
+        o = 0
+        for k in range(10):
+            b = b1 if k < 4 else b2
+            out[k, c] = (s >> o) & ((1 << b) - 1)
+            o += b
+    return out.reshape((10,) + w.shape[1:])
+
+
+def test_packed_16_16_is_the_paired_layout(orc):
+    m = W.random_moments(7, 5, 3, seed=1, dj=0.02, dp=0.003)
+    for mode in (0, 1):
+        assert np.array_equal(orc.qb_encode(m, 16, 16, t=4, seed=2, mode=mode), orc.q16_encode(m, t=4, seed=2, mode=mode))
+
+
+@pytest.mark.parametrize("b1,b2", CONFIGS)
+def test_packed_layout(orc, b1, b2):
+    rng = np.random.default_rng(b1 * 100 + b2)
+    q = np.stack([rng.integers(0, 1 << (b1 if k < 4 else b2), size=(3, 4, 5)) for k in range(10)]).astype(np.uint32)
+    w = orc.qb_pack(q, b1, b2)
+    assert w.shape[0] == -(-(4 * b1 + 6 * b2) // 32)
+    assert np.array_equal(_unpack_stream(w, b1, b2), q)
+
+
+@pytest.mark.parametrize("b1,b2", CONFIGS)
+def test_packed_known_answers(orc, b1, b2):
+    """min -> 0, max -> 2^b - 1, the range midpoint rounds half up (Sec. 5.3
+    with b bits), for every code of a cell."""
+    lo, hi = np.array(orc.Q_LO), np.array(orc.Q_HI)
+    b = np.array([b1] * 4 + [b2] * 6)
+    qmax = (1 << b) - 1
+    d = (hi - lo) / qmax
+    mid = 0.5 * (lo + hi)
+    vs = [lo, hi, mid + 0.05 * d, mid - 0.05 * d]
+    want = [np.zeros(10, int), qmax, (qmax + 1) // 2, (qmax - 1) // 2]
+    v = np.stack(vs, axis=1)  # codec variables (rho, u, N) of 4 cells
+    m = np.empty_like(v)
+    m[0] = v[0]
+    m[1:4] = v[0] * v[1:4]
+    pa, pb = [0, 1, 2, 0, 0, 1], [0, 1, 2, 1, 2, 2]
+    for p in range(6):
+        m[4 + p] = v[4 + p] + v[0] * v[1 + pa[p]] * v[1 + pb[p]]
+    w = orc.qb_encode(m.reshape(10, 1, 1, 4), b1, b2)
+    got = _unpack_stream(w, b1, b2).reshape(10, 4)
+    for c in range(4):
+        assert np.array_equal(got[:, c], want[c]), (c, got[:, c], want[c])
+
+
+@pytest.mark.parametrize("b1,b2", CONFIGS)
+def test_packed_round_trip_error(orc, b1, b2):
+    m = W.random_moments(9, 7, 5, seed=3, dj=0.02, dp=0.003)
+    lo, hi = np.array(orc.Q_LO), np.array(orc.Q_HI)
+    d = (hi - lo) / ((1 << np.array([b1] * 4 + [b2] * 6)) - 1)
+
+    def cvars(x):
+        rho = x[0]
+        u = x[1:4] / rho
+        pa, pb = [0, 1, 2, 0, 0, 1], [0, 1, 2, 1, 2, 2]
+        return np.stack([rho, *u, *[x[4 + p] - rho * u[pa[p]] * u[pb[p]] for p in range(6)]])
+
+    v = cvars(m)
+    for mode, bound in ((0, 0.5), (1, 1.0)):
+        r = cvars(orc.qb_decode(orc.qb_encode(m, b1, b2, t=1, seed=5, mode=mode), b1, b2))
+        err = np.abs(r - v).reshape(10, -1).max(axis=1)
+        assert np.all(err <= bound * d * (1 + 1e-3) + 1e-7), (mode, err / d)
