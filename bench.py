@@ -213,6 +213,56 @@ def channel(steps=20):
             "unhealthy_values": int(bad)}
 
 
+def bit_allocation(steps=2000, n=(128, 128, 32), tau=0.55):
+    """The b_rho_u / b_S study on a 3D double shear layer (the paper's
+    double-layer vortex, made three-dimensional by a z modulation of the
+    perturbation): the same run in FP32, 16-bit and each packed allocation;
+    relative L2 error of the velocity field against the FP32 run after
+    `steps` steps, bytes per cell, and the fluid pass's time per launch on
+    the 256^3 decaying-turbulence field for each format."""
+    import torch
+    from paper_2602_05295_amd import workloads as W
+    from paper_2602_05295_amd.homelbm import HomeLBM, BITS, FORMATS, raw_planes
+    nx, ny, nz = n
+    rho, u = W.double_shear_layer(nx, ny, nz, seed=0)
+    rho_d = torch.from_numpy(rho.astype(np.float32)).cuda()
+    u_d = torch.from_numpy(u.astype(np.float32)).cuda()
+    names = ["fp32", "q16", "p16_15", "p15_14", "p14_13", "p13_12", "p12_11"]
+    seeds = (0, 1, 2, 3)
+
+    def velocity(name, seed):
+        with HomeLBM((nx, ny, nz), tau, fmt=name) as s:
+            s.set_options(check_health=False, dither_mode=1, seed=seed)
+            s.set_equilibrium(rho_d, u_d)
+            s.step(steps)
+            m = s.get_moments()
+        return m[1:4] / m[0]
+
+    ref = velocity("fp32", 0)
+    errs = {name: [float(np.linalg.norm(velocity(name, sd) - ref) / np.linalg.norm(ref)) for sd in seeds]
+            for name in names[1:]}
+    rows = {}
+    rho2, u2 = workload()
+    r2 = torch.from_numpy(rho2).cuda()
+    v2 = torch.from_numpy(u2).cuda()
+    for name in names:
+        fmt = FORMATS[name]
+        with HomeLBM((N, N, N), TAU, fmt=name) as s:
+            s.set_options(check_health=False, dither_mode=1, seed=0)
+            s.set_equilibrium(r2, v2)
+            s.step(10)
+            prof = s.profile_steps(50)
+        e = errs.get(name, [0.0])
+        rows[name] = {"bits": None if name == "fp32" else "%d/%d" % BITS[fmt],
+                      "bytes_per_cell": 4 * raw_planes(fmt), "l2_rel_error_vs_fp32": round(float(np.mean(e)), 7),
+                      "l2_rel_error_min_max": [round(min(e), 7), round(max(e), 7)],
+                      "fluid_kernel_ms_256cubed": round(prof["fluid_ms"] / prof["fluid_launches"], 4)}
+    return {"config": "double shear layer %dx%dx%d, U0 0.04, tau %g, %d steps, error = mean over dither seeds %s "
+                      "of the relative L2 velocity difference from the FP32 run; kernel times on 256^3"
+                      % (nx, ny, nz, tau, steps, list(seeds)),
+            "formats": rows}
+
+
 def batched(steps=200):
     """128 periodic domains of seeded sizes 24^3..96^3 with sphere obstacles
     (0-10% solid) and tau in [0.52, 0.8], 16-bit moments: the autotuned work
@@ -276,7 +326,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--formats", default="q16,fp32", help="storage formats to run (the headline value is q16)")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint ratio and the channel run")
-    ap.add_argument("--only", choices=["adjoint", "channel", "batched"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "channel", "batched", "bits"], default=None,
                     help="run only this extra workload and print its JSON object (for profiling)")
     ap.add_argument("--extra-steps", type=int, default=None, help="steps of the --only workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -301,7 +351,7 @@ def main():
         print(f"[bench] copy calibration: 3 copies of {nbytes} bytes", file=sys.stderr, flush=True)
         del src, dst
     if args.only is not None:
-        fn = {"adjoint": adjoint_ratio, "channel": channel, "batched": batched}[args.only]
+        fn = {"adjoint": adjoint_ratio, "channel": channel, "batched": batched, "bits": bit_allocation}[args.only]
         kw = {} if args.extra_steps is None else {"steps": args.extra_steps}
         print(json.dumps(fn(**kw)), flush=True)
         return
@@ -325,7 +375,11 @@ def main():
         print("[bench] 128-domain batch", file=sys.stderr, flush=True)
         extras["batched"] = batched()
         print(f"[bench] {extras['batched']}", file=sys.stderr, flush=True)
-    print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        print("[bench] bit allocation (double shear layer)", file=sys.stderr, flush=True)
+        extras["bits"] = bit_allocation()
+        print(f"[bench] {extras['bits']}", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u)
     if "q16" not in res or "fp32" not in res:
         print(json.dumps({k: v for k, v in res.items()}), flush=True)
@@ -369,6 +423,7 @@ def main():
         "adjoint": extras.get("adjoint"),
         "channel_1000x400x400": extras.get("channel"),
         "batched_128_domains": extras.get("batched"),
+        "bit_allocation": extras.get("bits"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -52,8 +52,19 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Moment storage formats. */
 enum lbm_moment_format {
-  LBM_MOMENTS_FP32 = 0, /* ten float planes */
-  LBM_MOMENTS_Q16 = 1   /* five uint32 planes of paired 16-bit codes (Sec. 5.3) */
+  LBM_MOMENTS_FP32 = 0,   /* ten float planes */
+  LBM_MOMENTS_Q16 = 1,    /* five uint32 planes of paired 16-bit codes (Sec. 5.3) */
+  /* The b_rho_u / b_S bit allocations of the double-layer vortex study:
+   * the codes of rho and u take b_rho_u bits, those of the non-equilibrium
+   * stress b_S bits (Sec. 5.3's ranges, rounding and dither with b bits),
+   * concatenated low bit first in the order rho, ux, uy, uz, Nxx, Nyy, Nzz,
+   * Nxy, Nxz, Nyz into ceil((4 b_rho_u + 6 b_S)/32) uint32 planes (16/16 is
+   * the layout of LBM_MOMENTS_Q16).  Single-domain contexts only. */
+  LBM_MOMENTS_P16_15 = 2, /* 5 planes */
+  LBM_MOMENTS_P15_14 = 3, /* 5 planes */
+  LBM_MOMENTS_P14_13 = 4, /* 5 planes */
+  LBM_MOMENTS_P13_12 = 5, /* 4 planes, 16 B/cell */
+  LBM_MOMENTS_P12_11 = 6  /* 4 planes, 16 B/cell */
 };
 
 enum lbm_status {
@@ -80,7 +91,7 @@ typedef struct lbm_options {
   float u_in[3];      /* inflow velocity (used when inflow = 1) */
   int check_health;   /* 1 (default): lbm_step scans the state once at its end and
                          returns LBM_ERR_UNSTABLE if any stored value is non-finite
-                         (FP32) or any code sits at 0 or 65535 (Q16) */
+                         (FP32) or any code sits at 0 or its maximum (integer formats) */
   int tile_rows;      /* fluid-pass tile height: 0 (default) picks one from the grid
                          shape; 8, 10, 12 or 13 force it.  Results do not depend on it. */
   float force[3];     /* uniform body force F per cell and step, lattice units (App. A
@@ -137,7 +148,7 @@ int lbm_set_options(lbm_ctx* ctx, const lbm_options* opt);
 int lbm_get_options(const lbm_ctx* ctx, lbm_options* opt);
 
 /*
- * Sets the state from a full moment field (ten planes, see conventions).  Q16
+ * Sets the state from a full moment field (ten planes, see conventions).  Integer
  * contexts encode it without dither.  Solid cells are set to rest whatever m
  * holds there.
  */
@@ -165,7 +176,8 @@ int lbm_get_moments(lbm_ctx* ctx, float* m, int on_device);
  * Raw state copy.  FP32: ten float planes (40 B/cell) in the moment order
  * above except that plane 0 holds rho - 1 (for precision); Q16: five uint32 planes
  * (20 B/cell), word p of a cell packs code 2p in its low and code 2p+1 in its
- * high half, code order rho, ux, uy, uz, Nxx, Nyy, Nzz, Nxy, Nxz, Nyz.
+ * high half, code order rho, ux, uy, uz, Nxx, Nyy, Nzz, Nxy, Nxz, Nyz; the
+ * LBM_MOMENTS_P formats: their planes of packed codes (see the enum).
  * bytes must equal lbm_raw_bytes().
  */
 size_t lbm_raw_bytes(const lbm_ctx* ctx);

@@ -388,16 +388,19 @@ void dither(uint32_t idx, uint32_t t, uint32_t seed, int mode, double xi[10], ui
 
 // q = floor(m' (2^b - 1) + 1/2 + xi), m' = (m - min)/(max - min), saturated
 // (R5).  The decision is taken in single precision, the precision the GPU
-// library stores and computes in.
+// library stores and computes in, as q = rint(m' (2^b - 1) + xi) with exact
+// ties to even (R15): single precision puts m' (2^b - 1) on a grid of 1/512
+// or 1/256 of a step and the dither on a grid of 1/128, so exact ties occur
+// about once in 512 encodes, and sending them all up would add a systematic
+// +1/1024 step per encode, the bias the dither is there to remove.
 uint16_t encode_one(double m, int k, double xi) {
   const float mf = float(m);
   const float lo = float(Q_LO[k]);
   const float scale = float(double(QMAX) / (Q_HI[k] - Q_LO[k]));
-  const float v = (mf - lo) * scale + float(0.5 + xi);
+  const float v = std::nearbyint((mf - lo) * scale + float(xi));  // default rounding: to nearest, ties to even
   if (!(v >= 0.0f)) return 0;  // also maps NaN to 0
-  const float fl = std::floor(v);
-  if (fl >= float(QMAX)) return uint16_t(QMAX);
-  return uint16_t(fl);
+  if (v >= float(QMAX)) return uint16_t(QMAX);
+  return uint16_t(v);
 }
 
 double decode_one(uint32_t q, int k) { return Q_LO[k] + double(q) * ((Q_HI[k] - Q_LO[k]) / double(QMAX)); }
@@ -464,11 +467,10 @@ uint32_t encode_one_b(double m, int k, double xi, int b) {
   const float mf = float(m);
   const float lo = float(Q_LO[k]);
   const float scale = float(double(qmax) / (Q_HI[k] - Q_LO[k]));
-  const float v = (mf - lo) * scale + float(0.5 + xi);
+  const float v = std::nearbyint((mf - lo) * scale + float(xi));  // ties to even (R15)
   if (!(v >= 0.0f)) return 0;
-  const float fl = std::floor(v);
-  if (fl >= float(qmax)) return qmax;
-  return uint32_t(fl);
+  if (v >= float(qmax)) return qmax;
+  return uint32_t(v);
 }
 
 double decode_one_b(uint32_t q, int k, int b) {

@@ -29,7 +29,7 @@ ARCH = "gfx950"
 CFLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-Wall",
     # no packed FP32 (v_pk_*_f32) anywhere in device code

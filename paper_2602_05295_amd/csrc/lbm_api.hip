@@ -67,7 +67,7 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
 }
 
 size_t plane_bytes(const lbm_ctx* c) { return size_t(c->N) * 4; }
-int n_planes(const lbm_ctx* c) { return c->fmt == FMT_F32 ? 10 : 5; }
+int n_planes(const lbm_ctx* c) { return fmt_words(c->fmt); }
 size_t state_bytes(const lbm_ctx* c) { return plane_bytes(c) * n_planes(c); }
 
 void planes_of(const lbm_ctx* c, void* base, void* out[10]) {
@@ -192,7 +192,7 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   }
   p.g = geom(c);
   p.om1 = float(1.0 - 1.0 / c->tau);
-  const int mode = c->fmt == FMT_Q16 ? c->opt.dither_mode : 0;
+  const int mode = c->fmt != FMT_F32 ? c->opt.dither_mode : 0;
   p.dither = mode != 0;
   p.key = dither_key(uint32_t(c->t), c->opt.seed, mode);
   for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
@@ -274,7 +274,7 @@ int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_
   const int64_t N = int64_t(dims[0]) * dims[1] * dims[2];
   if (N > (int64_t(1) << 30)) return fail(nullptr, LBM_ERR_INVALID_ARG, "nx*ny*nz must be <= 2^30");
   if (!(tau > 0.5) || !std::isfinite(tau)) return fail(nullptr, LBM_ERR_INVALID_ARG, "tau must be > 1/2");
-  if (fmt != LBM_MOMENTS_FP32 && fmt != LBM_MOMENTS_Q16)
+  if (fmt < LBM_MOMENTS_FP32 || fmt > LBM_MOMENTS_P12_11)
     return fail(nullptr, LBM_ERR_INVALID_ARG, "unknown moment format");
   bool any_solid = false;
   if (mask)

@@ -1,6 +1,5 @@
 // lbm_aux.hip -- state set-up, read-back, health scan and the dither probe.
-#include "lbm_device.h"
-#include "lbm_internal.h"
+#include "lbm_codec.h"
 
 namespace lbm {
 
@@ -9,33 +8,45 @@ namespace {
 __device__ inline uint32_t grid_index() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
 // Encode full moments (rho, j, P) without dither (Sec. 5.3 codec).
-__device__ inline void encode_plain(const float m[10], uint32_t w[5]) {
+template <int FMT>
+__device__ inline void encode_plain(const float m[10], uint32_t* w) {
   const float rho = m[0];
   const float inv = 1.0f / rho;
   const float u[3] = {m[1] * inv, m[2] * inv, m[3] * inv};
   const float N[6] = {fmaf(-m[1], u[0], m[4]), fmaf(-m[2], u[1], m[5]), fmaf(-m[3], u[2], m[6]),
                       fmaf(-m[1], u[1], m[7]), fmaf(-m[1], u[2], m[8]), fmaf(-m[2], u[2], m[9])};
   uint32_t q[10];
-  q[0] = quantize(rho - Q_RHO_LO, Q_RHO_S, 0.5f);
+  if constexpr (FMT == FMT_Q16) {
+    q[0] = quantize(rho - Q_RHO_LO, Q_RHO_S, 0.0f);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) q[1 + a] = quantize(u[a] - Q_U_LO, Q_U_S, 0.5f);
+    for (int a = 0; a < 3; ++a) q[1 + a] = quantize(u[a] - Q_U_LO, Q_U_S, 0.0f);
 #pragma unroll
-  for (int p = 0; p < 6; ++p) q[4 + p] = quantize(N[p] - Q_N_LO, Q_N_S, 0.5f);
+    for (int p = 0; p < 6; ++p) q[4 + p] = quantize(N[p] - Q_N_LO, Q_N_S, 0.0f);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) w[k] = q[2 * k] | (q[2 * k + 1] << 16);
+    for (int k = 0; k < 5; ++k) w[k] = q[2 * k] | (q[2 * k + 1] << 16);
+  } else {
+    using PK = typename Codec<FMT>::PK;
+    q[0] = quantize_b(rho - Q_RHO_LO, PK::SR, 0.0f, PK::qmax(0));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[1 + a] = quantize_b(u[a] - Q_U_LO, PK::SU, 0.0f, PK::qmax(1));
+#pragma unroll
+    for (int p = 0; p < 6; ++p) q[4 + p] = quantize_b(N[p] - Q_N_LO, PK::SN, 0.0f, PK::qmax(4));
+    pack_codes<PK>(q, w);
+  }
 }
 
 // Writes full moments (rho, j, P); the FP32 state keeps rho - 1 in plane 0.
-__device__ inline void write_state(int fmt, void* const out[10], uint32_t c, const float m[10]) {
-  if (fmt == FMT_F32) {
+template <int FMT>
+__device__ inline void write_state(void* const out[10], uint32_t c, const float m[10]) {
+  if constexpr (FMT == FMT_F32) {
     static_cast<float*>(out[0])[c] = m[0] - 1.0f;
 #pragma unroll
     for (int k = 1; k < 10; ++k) static_cast<float*>(out[k])[c] = m[k];
   } else {
-    uint32_t w[5];
-    encode_plain(m, w);
+    uint32_t w[Codec<FMT>::W];
+    encode_plain<FMT>(m, w);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) static_cast<uint32_t*>(out[k])[c] = w[k];
+    for (int k = 0; k < Codec<FMT>::W; ++k) static_cast<uint32_t*>(out[k])[c] = w[k];
   }
 }
 
@@ -46,7 +57,8 @@ struct CPlanes10 {
   const void* p[10];
 };
 
-__global__ void set_moments_kernel(int fmt, const float* __restrict__ m, Planes10 out, const uint8_t* __restrict__ mask,
+template <int FMT>
+__global__ void set_moments_kernel(const float* __restrict__ m, Planes10 out, const uint8_t* __restrict__ mask,
                                    uint32_t N) {
   const uint32_t c = grid_index();
   if (c >= N) return;
@@ -55,11 +67,12 @@ __global__ void set_moments_kernel(int fmt, const float* __restrict__ m, Planes1
 #pragma unroll
     for (int k = 0; k < 10; ++k) v[k] = m[size_t(k) * N + c];
   }
-  write_state(fmt, out.p, c, v);
+  write_state<FMT>(out.p, c, v);
 }
 
-__global__ void set_equilibrium_kernel(int fmt, const float* __restrict__ rho, const float* __restrict__ u,
-                                       Planes10 out, const uint8_t* __restrict__ mask, uint32_t N) {
+template <int FMT>
+__global__ void set_equilibrium_kernel(const float* __restrict__ rho, const float* __restrict__ u, Planes10 out,
+                                       const uint8_t* __restrict__ mask, uint32_t N) {
   const uint32_t c = grid_index();
   if (c >= N) return;
   float v[10] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -77,24 +90,24 @@ __global__ void set_equilibrium_kernel(int fmt, const float* __restrict__ rho, c
     v[8] = v[1] * uz;
     v[9] = v[2] * uz;
   }
-  write_state(fmt, out.p, c, v);
+  write_state<FMT>(out.p, c, v);
 }
 
-__global__ void get_moments_kernel(int fmt, CPlanes10 in, float* __restrict__ m, const uint8_t* __restrict__ mask,
-                                   uint32_t N) {
+template <int FMT>
+__global__ void get_moments_kernel(CPlanes10 in, float* __restrict__ m, const uint8_t* __restrict__ mask, uint32_t N) {
   const uint32_t c = grid_index();
   if (c >= N) return;
   float v[10] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (!(mask && mask[c])) {
-    if (fmt == FMT_F32) {
+    if constexpr (FMT == FMT_F32) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) v[k] = static_cast<const float*>(in.p[k])[c];
       v[0] += 1.0f;
     } else {
-      uint32_t w[5];
+      uint32_t w[Codec<FMT>::W];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) w[k] = static_cast<const uint32_t*>(in.p[k])[c];
-      const CellIn q = cell_from_words(w);
+      for (int k = 0; k < Codec<FMT>::W; ++k) w[k] = static_cast<const uint32_t*>(in.p[k])[c];
+      const CellIn q = Codec<FMT>::decode(w);
       v[0] = q.rho;
       v[1] = q.rho * q.u[0];
       v[2] = q.rho * q.u[1];
@@ -111,20 +124,19 @@ __global__ void get_moments_kernel(int fmt, CPlanes10 in, float* __restrict__ m,
   for (int k = 0; k < 10; ++k) m[size_t(k) * N + c] = v[k];
 }
 
-__global__ void health_kernel(int fmt, CPlanes10 in, uint32_t N, unsigned long long* bad) {
+template <int FMT>
+__global__ void health_kernel(CPlanes10 in, uint32_t N, unsigned long long* bad) {
   const uint32_t c = grid_index();
   uint32_t n = 0;
   if (c < N) {
-    if (fmt == FMT_F32) {
+    if constexpr (FMT == FMT_F32) {
 #pragma unroll
       for (int k = 0; k < 10; ++k) n += isfinite(static_cast<const float*>(in.p[k])[c]) ? 0u : 1u;
     } else {
+      uint32_t w[Codec<FMT>::W];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const uint32_t w = static_cast<const uint32_t*>(in.p[k])[c];
-        n += (lo16(w) == 0u || lo16(w) == 0xFFFFu) ? 1u : 0u;
-        n += (hi16(w) == 0u || hi16(w) == 0xFFFFu) ? 1u : 0u;
-      }
+      for (int k = 0; k < Codec<FMT>::W; ++k) w[k] = static_cast<const uint32_t*>(in.p[k])[c];
+      n = Codec<FMT>::saturated(w);
     }
   }
   // one atomic per wavefront with offenders
@@ -135,11 +147,23 @@ __global__ void health_kernel(int fmt, CPlanes10 in, uint32_t N, unsigned long l
   if (__lane_id() == __ffsll(static_cast<long long>(vote)) - 1) atomicAdd(bad, static_cast<unsigned long long>(tot));
 }
 
-__global__ void set_rest_kernel(int fmt, Planes10 out, uint32_t N) {
+template <int FMT>
+__global__ void set_rest_kernel(Planes10 out, uint32_t N) {
   const uint32_t c = grid_index();
   if (c >= N) return;
   const float v[10] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  write_state(fmt, out.p, c, v);
+  write_state<FMT>(out.p, c, v);
+}
+
+// Runs f.template operator()<FMT>() for any stored format.
+template <class Fn>
+hipError_t for_format(int fmt, Fn&& f) {
+  if (fmt == FMT_F32) {
+    f.template operator()<FMT_F32>();
+  } else if (!dispatch_codes(fmt, f)) {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 __global__ void debug_dither_kernel(int n, const uint32_t* __restrict__ idx, uint32_t key, uint32_t* __restrict__ out) {
@@ -159,38 +183,43 @@ hipError_t launch_set_moments(int fmt, const float* m, void* const out[10], cons
                               hipStream_t s) {
   Planes10 o;
   for (int k = 0; k < 10; ++k) o.p[k] = out[k];
-  hipLaunchKernelGGL(set_moments_kernel, grid_for(N), dim3(256), 0, s, fmt, m, o, mask, uint32_t(N));
-  return hipGetLastError();
+  return for_format(fmt, [&]<int F>() {
+    hipLaunchKernelGGL(set_moments_kernel<F>, grid_for(N), dim3(256), 0, s, m, o, mask, uint32_t(N));
+  });
 }
 
 hipError_t launch_set_equilibrium(int fmt, const float* rho, const float* u, void* const out[10],
                                   const uint8_t* mask, int64_t N, hipStream_t s) {
   Planes10 o;
   for (int k = 0; k < 10; ++k) o.p[k] = out[k];
-  hipLaunchKernelGGL(set_equilibrium_kernel, grid_for(N), dim3(256), 0, s, fmt, rho, u, o, mask, uint32_t(N));
-  return hipGetLastError();
+  return for_format(fmt, [&]<int F>() {
+    hipLaunchKernelGGL(set_equilibrium_kernel<F>, grid_for(N), dim3(256), 0, s, rho, u, o, mask, uint32_t(N));
+  });
 }
 
 hipError_t launch_get_moments(int fmt, const void* const in[10], float* m, const uint8_t* mask, int64_t N,
                               hipStream_t s) {
   CPlanes10 i;
   for (int k = 0; k < 10; ++k) i.p[k] = in[k];
-  hipLaunchKernelGGL(get_moments_kernel, grid_for(N), dim3(256), 0, s, fmt, i, m, mask, uint32_t(N));
-  return hipGetLastError();
+  return for_format(fmt, [&]<int F>() {
+    hipLaunchKernelGGL(get_moments_kernel<F>, grid_for(N), dim3(256), 0, s, i, m, mask, uint32_t(N));
+  });
 }
 
 hipError_t launch_health(int fmt, const void* const in[10], int64_t N, unsigned long long* bad, hipStream_t s) {
   CPlanes10 i;
   for (int k = 0; k < 10; ++k) i.p[k] = in[k];
-  hipLaunchKernelGGL(health_kernel, grid_for(N), dim3(256), 0, s, fmt, i, uint32_t(N), bad);
-  return hipGetLastError();
+  return for_format(fmt, [&]<int F>() {
+    hipLaunchKernelGGL(health_kernel<F>, grid_for(N), dim3(256), 0, s, i, uint32_t(N), bad);
+  });
 }
 
 hipError_t launch_set_rest(int fmt, void* const out[10], int64_t N, hipStream_t s) {
   Planes10 o;
   for (int k = 0; k < 10; ++k) o.p[k] = out[k];
-  hipLaunchKernelGGL(set_rest_kernel, grid_for(N), dim3(256), 0, s, fmt, o, uint32_t(N));
-  return hipGetLastError();
+  return for_format(fmt, [&]<int F>() {
+    hipLaunchKernelGGL(set_rest_kernel<F>, grid_for(N), dim3(256), 0, s, o, uint32_t(N));
+  });
 }
 
 hipError_t launch_debug_dither(int n, const uint32_t* idx, uint32_t key, uint32_t* out, hipStream_t s) {

@@ -546,6 +546,8 @@ int lbm_batch_create(int count, const int* dims, const double* taus, const uint8
   *out = nullptr;
   if (count < 1 || count > 65535) return bfail(nullptr, LBM_ERR_INVALID_ARG, "count must be in 1..65535");
   if (!dims || !taus) return bfail(nullptr, LBM_ERR_INVALID_ARG, "dims or taus is NULL");
+  if (fmt >= LBM_MOMENTS_P16_15 && fmt <= LBM_MOMENTS_P12_11)
+    return bfail(nullptr, LBM_ERR_UNSUPPORTED, "batches store FP32 or 16-bit moments");
   if (fmt != LBM_MOMENTS_FP32 && fmt != LBM_MOMENTS_Q16)
     return bfail(nullptr, LBM_ERR_INVALID_ARG, "unknown moment format");
   int64_t total = 0;

@@ -50,34 +50,34 @@ __global__ void __launch_bounds__(256) boundary_solid_kernel(StepParams a, const
   boundary_solid<FMT>(a, cells[e]);
 }
 
-hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
-                           const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
+namespace {
+template <int FMT>
+hipError_t launch_boundary_fmt(const StepParams& p, const uint32_t* cells, const uint32_t* bits, const uint32_t* yz,
+                               const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
   if (nfluid > 0) {
     const dim3 grid(uint32_t((nfluid + 255) / 256));
-    if (p.forces) {
-      if (fmt == FMT_F32)
-        hipLaunchKernelGGL(boundary_fluid_forces_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, order,
-                           nfluid);
-      else
-        hipLaunchKernelGGL(boundary_fluid_forces_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, order,
-                           nfluid);
-    } else if (fmt == FMT_F32) {
-      hipLaunchKernelGGL(boundary_fluid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
-    } else {
-      hipLaunchKernelGGL(boundary_fluid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
-    }
+    if (p.forces)
+      hipLaunchKernelGGL(boundary_fluid_forces_kernel<FMT>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
+    else
+      hipLaunchKernelGGL(boundary_fluid_kernel<FMT>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (nsolid > 0) {
     const dim3 grid(uint32_t((nsolid + 255) / 256));
-    if (fmt == FMT_F32)
-      hipLaunchKernelGGL(boundary_solid_kernel<FMT_F32>, grid, dim3(256), 0, s, p, cells + nfluid, nsolid);
-    else
-      hipLaunchKernelGGL(boundary_solid_kernel<FMT_Q16>, grid, dim3(256), 0, s, p, cells + nfluid, nsolid);
+    hipLaunchKernelGGL(boundary_solid_kernel<FMT>, grid, dim3(256), 0, s, p, cells + nfluid, nsolid);
     return hipGetLastError();
   }
   return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
+                           const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
+  if (fmt == FMT_F32) return launch_boundary_fmt<FMT_F32>(p, cells, bits, yz, order, nfluid, nsolid, s);
+  hipError_t e = hipErrorInvalidValue;
+  dispatch_codes(fmt, [&]<int F>() { e = launch_boundary_fmt<F>(p, cells, bits, yz, order, nfluid, nsolid, s); });
+  return e;
 }
 
 // ------------------------------------------------------------ compaction ---

@@ -15,8 +15,7 @@
 // rest.
 #pragma once
 
-#include "lbm_device.h"
-#include "lbm_internal.h"
+#include "lbm_codec.h"
 
 namespace lbm {
 
@@ -71,10 +70,11 @@ __device__ inline CellIn load_cell_b(const StepParams& a, uint32_t cell) {
     for (int k = 0; k < 10; ++k) m[k] = *reinterpret_cast<const float*>(static_cast<const char*>(a.in[k]) + off);
     return cell_from_moments(m);
   } else {
-    uint32_t w[5];
+    uint32_t w[Codec<FMT>::W];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) w[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + off);
-    return cell_from_words(w);
+    for (int k = 0; k < Codec<FMT>::W; ++k)
+      w[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + off);
+    return Codec<FMT>::decode(w);
   }
 }
 
@@ -86,23 +86,11 @@ __device__ inline void store_cell_b(const StepParams& a, uint32_t cell, float dr
 #pragma unroll
     for (int k = 0; k < 10; ++k) *reinterpret_cast<float*>(static_cast<char*>(a.out[k]) + off) = v[k];
   } else {
-    uint32_t w[5];
-    encode_cell(dr, j, P, cell, a.key, a.dither != 0, w);
+    uint32_t w[Codec<FMT>::W];
+    Codec<FMT>::encode(dr, j, P, cell, a.key, a.dither != 0, w);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
+    for (int k = 0; k < Codec<FMT>::W; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
   }
-}
-
-// Code words of the rest state (rho = 1, u = 0, N = 0), rounded without dither.
-__device__ inline void rest_words(uint32_t w[5]) {
-  const uint32_t qr = quantize(1.0f - Q_RHO_LO, Q_RHO_S, 0.5f);
-  const uint32_t qu = quantize(0.0f - Q_U_LO, Q_U_S, 0.5f);
-  const uint32_t qn = quantize(0.0f - Q_N_LO, Q_N_S, 0.5f);
-  w[0] = qr | (qu << 16);
-  w[1] = qu | (qu << 16);
-  w[2] = qn | (qn << 16);
-  w[3] = qn | (qn << 16);
-  w[4] = qn | (qn << 16);
 }
 
 // Post-collision coefficients of cell q (with the inflow velocity when
@@ -201,9 +189,9 @@ __device__ inline void rest_coeffs(const StepParams& a, float A[NA]) {
     const float m[10] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     c = cell_from_moments(m);
   } else {
-    uint32_t w[5];
-    rest_words(w);
-    c = cell_from_words(w);
+    uint32_t w[Codec<FMT>::W];
+    rest_codes<FMT>(w);
+    c = Codec<FMT>::decode(w);
   }
   if (a.force)
     post_collision<true>(c, a.om1, a.hF, A);
@@ -319,10 +307,10 @@ __device__ inline void boundary_solid(const StepParams& a, uint32_t cell) {
     const float j[3] = {0, 0, 0}, P[6] = {0, 0, 0, 0, 0, 0};
     store_cell_b<FMT>(a, cell, 0.0f, j, P);
   } else {
-    uint32_t w[5];
-    rest_words(w);
+    uint32_t w[Codec<FMT>::W];
+    rest_codes<FMT>(w);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + cell * 4u) = w[k];
+    for (int k = 0; k < Codec<FMT>::W; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + cell * 4u) = w[k];
   }
 }
 

@@ -22,6 +22,8 @@
 // density's discrete Laplacian, would inherit errors near 1e-5 of its size.
 #pragma once
 
+#include <utility>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,21 +66,27 @@ __device__ inline void dither_words(uint32_t idx, uint32_t key, uint32_t& h1, ui
   h2 = pcg_hash(h1 ^ 0x9E3779B9u);
 }
 
-// 1/2 + xi = (v + 1/2)/64 for component k, the 6-bit field v of the hash
-// words.  Without dither the words are 0 and base is 1/2, which gives 1/2.
+// xi = (v + 1/2)/64 - 1/2 for component k, the 6-bit field v of the hash
+// words; 0 without dither.
 template <int K>
-__device__ inline float half_plus_xi(uint32_t h1, uint32_t h2, float base) {
+__device__ inline float dither_xi(uint32_t h1, uint32_t h2, bool dith) {
   const uint32_t src = (K < 5) ? h1 : h2;
   const uint32_t v = (src >> (6 * (K % 5))) & 63u;
-  return fmaf(float(v), 1.0f / 64.0f, base);
+  return dith ? fmaf(float(v), 1.0f / 64.0f, 1.0f / 128.0f - 0.5f) : 0.0f;
 }
 
-// floor((m - lo) * s + (1/2 + xi)), saturated to [0, 65535].
-__device__ inline uint32_t quantize(float d_from_lo, float s, float hpx) {
-  float v = fmaf(d_from_lo, s, hpx);
-  v = fminf(fmaxf(v, 0.0f), QMAXF);
+// The code of Sec. 5.3, floor(m' (2^b - 1) + 1/2 + xi), taken in single
+// precision as rint((m - lo) s + xi) with exact ties to even, saturated to
+// [0, qmax].  Single precision puts (m - lo) s on a grid of 1/512 or 1/256 of
+// a step near the middle of the range and the dither on a grid of 1/128, so
+// exact ties occur about once in 512 encodes; sending them all up would add
+// +1/1024 of a step per encode, the bias the dither is there to remove.
+__device__ inline uint32_t quantize_b(float d_from_lo, float s, float xi, uint32_t qmax) {
+  float v = __builtin_rintf(fmaf(d_from_lo, s, xi));
+  v = fminf(fmaxf(v, 0.0f), float(qmax));
   return uint32_t(v);
 }
+__device__ inline uint32_t quantize(float d_from_lo, float s, float xi) { return quantize_b(d_from_lo, s, xi, 65535u); }
 
 __device__ inline uint32_t lo16(uint32_t w) { return w & 0xFFFFu; }
 __device__ inline uint32_t hi16(uint32_t w) { return w >> 16; }
@@ -415,15 +423,14 @@ __device__ inline void coeffs_T(const CellLin& c, float om1, const float gA[NA],
 // New moments (dr = rho - 1, j, P) -> five code words: u = j / rho,
 // N = P - j u, each normalised, dithered, rounded and saturated (Sec. 5.3).
 //
-// v_cvt_pknorm_u16_f32 returns floor(clamp(x, 0, 1) * 65535 + 1/2) for every
-// float x (round to nearest; ties cannot occur because 65535 x + 1/2 is never
-// an integer for a binary x in (0, 1)), for two values at once.  With
+// v_cvt_pknorm_u16_f32 rounds clamp(x, 0, 1) * 65535 to the nearest integer
+// without first rounding the product, for two values at once.  With
 // x = (m - min)/(max - min) + xi/65535 it gives the paper's
 // q = floor(m' (2^16 - 1) + 1/2 + xi) including the saturation, from one fma
-// per value.
-#ifndef LBM_PKNORM_ENCODE
-#define LBM_PKNORM_ENCODE 1
-#endif
+// per value.  Since the product is exact, the only float x that falls on a
+// tie is x = 1/2 (rounded to even), so the rounding adds no bias; an encode
+// that forms (m - min) s in single precision first meets ties once in about
+// 512 encodes and rounds them to even (quantize_b).
 constexpr float QN_RHO_S = float(1.0 / 0.7), QN_RHO_C = float(0.2 / 0.7);  // x = (rho - 1)/0.7 + 0.2/0.7
 constexpr float QN_U_S = float(1.0 / 0.8), QN_U_C = 0.5f;
 constexpr float QN_N_S = float(1.0 / 0.2), QN_N_C = 0.5f;
@@ -454,7 +461,6 @@ __device__ inline void encode_cell(float dr, const float j[3], const float P[6],
                       fmaf(-j[0], u[1], P[3]), fmaf(-j[0], u[2], P[4]), fmaf(-j[1], u[2], P[5])};
   uint32_t h1 = 0, h2 = 0;
   if (dith) dither_words(cell, key, h1, h2);
-#if LBM_PKNORM_ENCODE
   const float x0 = dith ? QN_XI0 : 0.0f;
   const float cr = QN_RHO_C + x0, cu = QN_U_C + x0, cn = QN_N_C + x0;
   w[0] = pknorm2(fmaf(dr, QN_RHO_S, xi_norm<0>(h1, h2, cr)), fmaf(u[0], QN_U_S, xi_norm<1>(h1, h2, cu)));
@@ -462,24 +468,113 @@ __device__ inline void encode_cell(float dr, const float j[3], const float P[6],
   w[2] = pknorm2(fmaf(N[0], QN_N_S, xi_norm<4>(h1, h2, cn)), fmaf(N[1], QN_N_S, xi_norm<5>(h1, h2, cn)));
   w[3] = pknorm2(fmaf(N[2], QN_N_S, xi_norm<6>(h1, h2, cn)), fmaf(N[3], QN_N_S, xi_norm<7>(h1, h2, cn)));
   w[4] = pknorm2(fmaf(N[4], QN_N_S, xi_norm<8>(h1, h2, cn)), fmaf(N[5], QN_N_S, xi_norm<9>(h1, h2, cn)));
-#else
-  const float base = dith ? 1.0f / 128.0f : 0.5f;
-  const uint32_t q0 = quantize(dr - Q_DRHO_LO, Q_RHO_S, half_plus_xi<0>(h1, h2, base));
-  const uint32_t q1 = quantize(u[0] - Q_U_LO, Q_U_S, half_plus_xi<1>(h1, h2, base));
-  const uint32_t q2 = quantize(u[1] - Q_U_LO, Q_U_S, half_plus_xi<2>(h1, h2, base));
-  const uint32_t q3 = quantize(u[2] - Q_U_LO, Q_U_S, half_plus_xi<3>(h1, h2, base));
-  const uint32_t q4 = quantize(N[0] - Q_N_LO, Q_N_S, half_plus_xi<4>(h1, h2, base));
-  const uint32_t q5 = quantize(N[1] - Q_N_LO, Q_N_S, half_plus_xi<5>(h1, h2, base));
-  const uint32_t q6 = quantize(N[2] - Q_N_LO, Q_N_S, half_plus_xi<6>(h1, h2, base));
-  const uint32_t q7 = quantize(N[3] - Q_N_LO, Q_N_S, half_plus_xi<7>(h1, h2, base));
-  const uint32_t q8 = quantize(N[4] - Q_N_LO, Q_N_S, half_plus_xi<8>(h1, h2, base));
-  const uint32_t q9 = quantize(N[5] - Q_N_LO, Q_N_S, half_plus_xi<9>(h1, h2, base));
-  w[0] = q0 | (q1 << 16);
-  w[1] = q2 | (q3 << 16);
-  w[2] = q4 | (q5 << 16);
-  w[3] = q6 | (q7 << 16);
-  w[4] = q8 | (q9 << 16);
-#endif
+}
+
+// ------------------------------------------- packed b_rho_u / b_S codes ---
+// Codes of rho and u with B1 bits, of the non-equilibrium stress with B2 bits
+// (Sec. 5.3's ranges, rounding and dither with b bits), concatenated low bit
+// first in the order rho, ux, uy, uz, Nxx, Nyy, Nzz, Nxy, Nxz, Nyz into
+// W = ceil((4 B1 + 6 B2)/32) words: code k occupies bits [o_k, o_k + b_k)
+// of the cell's words read as one little-endian integer.
+template <int B1, int B2>
+struct Packed {
+  static constexpr int W = (4 * B1 + 6 * B2 + 31) / 32;
+  static constexpr int bits(int k) { return k < 4 ? B1 : B2; }
+  static constexpr int off(int k) { return k < 4 ? k * B1 : 4 * B1 + (k - 4) * B2; }
+  static constexpr uint32_t qmax(int k) { return (1u << bits(k)) - 1u; }
+  // decode steps (range / (2^b - 1)) and encode scales ((2^b - 1) / range)
+  static constexpr float DR = float(0.7 / double((1u << B1) - 1u));
+  static constexpr float DU = float(0.8 / double((1u << B1) - 1u));
+  static constexpr float DN = float(0.2 / double((1u << B2) - 1u));
+  static constexpr float SR = float(double((1u << B1) - 1u) / 0.7);
+  static constexpr float SU = float(double((1u << B1) - 1u) / 0.8);
+  static constexpr float SN = float(double((1u << B2) - 1u) / 0.2);
+};
+
+// Code k of a cell's packed words.
+template <class PK, int K>
+__device__ inline uint32_t packed_code(const uint32_t* w) {
+  constexpr int o = PK::off(K), b = PK::bits(K), i = o / 32, s = o % 32;
+  constexpr uint32_t mask = (1u << b) - 1u;
+  if constexpr (s + b <= 32) {
+    return (w[i] >> s) & mask;
+  } else {
+    return ((w[i] >> s) | (w[i + 1] << (32 - s))) & mask;
+  }
+}
+
+template <class PK>
+__device__ inline void packed_codes(const uint32_t* w, uint32_t q[10]) {
+  q[0] = packed_code<PK, 0>(w);
+  q[1] = packed_code<PK, 1>(w);
+  q[2] = packed_code<PK, 2>(w);
+  q[3] = packed_code<PK, 3>(w);
+  q[4] = packed_code<PK, 4>(w);
+  q[5] = packed_code<PK, 5>(w);
+  q[6] = packed_code<PK, 6>(w);
+  q[7] = packed_code<PK, 7>(w);
+  q[8] = packed_code<PK, 8>(w);
+  q[9] = packed_code<PK, 9>(w);
+}
+
+// Adds code K to the words: every index and shift is a constant.
+template <class PK, int K>
+__device__ inline void pack_code(uint32_t q, uint32_t* w) {
+  constexpr int o = PK::off(K), b = PK::bits(K), i = o / 32, s = o % 32;
+  w[i] |= q << s;
+  if constexpr (s + b > 32) w[i + 1] |= q >> (32 - s);
+}
+
+template <class PK, int... K>
+__device__ inline void pack_all(const uint32_t q[10], uint32_t* w, std::integer_sequence<int, K...>) {
+  (pack_code<PK, K>(q[K], w), ...);
+}
+
+template <class PK>
+__device__ inline void pack_codes(const uint32_t q[10], uint32_t* w) {
+#pragma unroll
+  for (int i = 0; i < PK::W; ++i) w[i] = 0u;
+  pack_all<PK>(q, w, std::make_integer_sequence<int, 10>{});
+}
+
+template <class PK>
+__device__ inline CellIn cell_from_packed(const uint32_t* w) {
+  uint32_t q[10];
+  packed_codes<PK>(w, q);
+  CellIn c;
+  c.dr = fmaf(float(q[0]), PK::DR, Q_DRHO_LO);
+  c.rho = c.dr + 1.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.u[a] = fmaf(float(q[1 + a]), PK::DU, Q_U_LO);
+#pragma unroll
+  for (int p = 0; p < 6; ++p) c.N[p] = fmaf(float(q[4 + p]), PK::DN, Q_N_LO);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c.j[a] = c.rho * c.u[a];
+  return c;
+}
+
+
+template <class PK>
+__device__ inline void encode_packed(float dr, const float j[3], const float P[6], uint32_t cell, uint32_t key,
+                                     bool dith, uint32_t* w) {
+  const float inv = __builtin_amdgcn_rcpf(1.0f + dr);
+  const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
+  const float N[6] = {fmaf(-j[0], u[0], P[0]), fmaf(-j[1], u[1], P[1]), fmaf(-j[2], u[2], P[2]),
+                      fmaf(-j[0], u[1], P[3]), fmaf(-j[0], u[2], P[4]), fmaf(-j[1], u[2], P[5])};
+  uint32_t h1 = 0, h2 = 0;
+  if (dith) dither_words(cell, key, h1, h2);
+  uint32_t q[10];
+  q[0] = quantize_b(dr - Q_DRHO_LO, PK::SR, dither_xi<0>(h1, h2, dith), PK::qmax(0));
+  q[1] = quantize_b(u[0] - Q_U_LO, PK::SU, dither_xi<1>(h1, h2, dith), PK::qmax(1));
+  q[2] = quantize_b(u[1] - Q_U_LO, PK::SU, dither_xi<2>(h1, h2, dith), PK::qmax(2));
+  q[3] = quantize_b(u[2] - Q_U_LO, PK::SU, dither_xi<3>(h1, h2, dith), PK::qmax(3));
+  q[4] = quantize_b(N[0] - Q_N_LO, PK::SN, dither_xi<4>(h1, h2, dith), PK::qmax(4));
+  q[5] = quantize_b(N[1] - Q_N_LO, PK::SN, dither_xi<5>(h1, h2, dith), PK::qmax(5));
+  q[6] = quantize_b(N[2] - Q_N_LO, PK::SN, dither_xi<6>(h1, h2, dith), PK::qmax(6));
+  q[7] = quantize_b(N[3] - Q_N_LO, PK::SN, dither_xi<7>(h1, h2, dith), PK::qmax(7));
+  q[8] = quantize_b(N[4] - Q_N_LO, PK::SN, dither_xi<8>(h1, h2, dith), PK::qmax(8));
+  q[9] = quantize_b(N[5] - Q_N_LO, PK::SN, dither_xi<9>(h1, h2, dith), PK::qmax(9));
+  pack_codes<PK>(q, w);
 }
 
 // ------------------------------------------------------------ int helpers ---

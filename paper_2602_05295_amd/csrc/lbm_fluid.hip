@@ -28,8 +28,7 @@
 // compact band of tiles.  The host picks the tile height and S from the
 // domain shape.  Every axis is treated as periodic here; faces and walls are
 // overwritten afterwards by the boundary pass.
-#include "lbm_device.h"
-#include "lbm_internal.h"
+#include "lbm_codec.h"
 
 #include <algorithm>
 
@@ -51,27 +50,24 @@ struct FluidLds {
   float lx[18][TYR][RW + 2];  // x movers (+, -) of 9 groups, with halo columns at 0 and RW + 1
 };
 
-template <int FMT>
-struct Raw;
-template <>
-struct Raw<FMT_F32> {
+// The stored words of one cell: ten floats, or the format's code words.
+template <int FMT, bool F = (FMT == FMT_F32)>
+struct Raw {
+  static constexpr int K = 10;
   float v[10];
 };
-template <>
-struct Raw<FMT_Q16> {
-  uint32_t v[5];
+template <int FMT>
+struct Raw<FMT, false> {
+  static constexpr int K = Codec<FMT>::W;
+  uint32_t v[Codec<FMT>::W];
 };
 
 template <int FMT>
 __device__ inline Raw<FMT> load_raw(const StepParams& a, uint32_t off) {
   Raw<FMT> r;
-  if constexpr (FMT == FMT_F32) {
+  using T = decltype(r.v[0] + 0);
 #pragma unroll
-    for (int k = 0; k < 10; ++k) r.v[k] = *reinterpret_cast<const float*>(static_cast<const char*>(a.in[k]) + off);
-  } else {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) r.v[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + off);
-  }
+  for (int k = 0; k < Raw<FMT>::K; ++k) r.v[k] = *reinterpret_cast<const T*>(static_cast<const char*>(a.in[k]) + off);
   return r;
 }
 
@@ -80,9 +76,8 @@ __device__ inline Raw<FMT> load_raw(const StepParams& a, uint32_t off) {
 // memory operation may cross (so none issued after it is waited for).
 template <int FMT>
 __device__ inline void state_arrived(const Raw<FMT>& r) {
-  constexpr int K = FMT == FMT_F32 ? 10 : 5;
 #pragma unroll
-  for (int k = 0; k < K; ++k) asm volatile("" : : "v"(r.v[k]) : "memory");
+  for (int k = 0; k < Raw<FMT>::K; ++k) asm volatile("" : : "v"(r.v[k]) : "memory");
 }
 
 template <int FMT>
@@ -90,7 +85,7 @@ __device__ inline CellIn decode(const Raw<FMT>& r) {
   if constexpr (FMT == FMT_F32)
     return cell_from_moments(r.v);
   else
-    return cell_from_words(r.v);
+    return Codec<FMT>::decode(r.v);
 }
 
 // Writes the new moments of one cell: dr = rho - 1, j, P (xx yy zz xy xz yz).
@@ -102,10 +97,10 @@ __device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, 
 #pragma unroll
     for (int k = 0; k < 10; ++k) *reinterpret_cast<float*>(static_cast<char*>(a.out[k]) + off) = v[k];
   } else {
-    uint32_t w[5];
-    encode_cell(dr, j, P, cell, a.key, a.dither != 0, w);
+    uint32_t w[Codec<FMT>::W];
+    Codec<FMT>::encode(dr, j, P, cell, a.key, a.dither != 0, w);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
+    for (int k = 0; k < Codec<FMT>::W; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
   }
 }
 
@@ -417,8 +412,12 @@ hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {
   if (fmt == FMT_F32)
     return p.force ? launch_rows<FMT_F32, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
                    : launch_rows<FMT_F32, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
-  return p.force ? launch_rows<FMT_Q16, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
-                 : launch_rows<FMT_Q16, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  hipError_t e = hipErrorInvalidValue;
+  dispatch_codes(fmt, [&]<int F>() {
+    e = p.force ? launch_rows<F, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
+                : launch_rows<F, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  });
+  return e;
 }
 
 }  // namespace lbm

@@ -6,7 +6,17 @@
 
 namespace lbm {
 
-enum Format { FMT_F32 = 0, FMT_Q16 = 1 };
+// FMT_P<b1>_<b2>: the b_rho_u / b_S allocations of the double-layer vortex
+// study (codes of rho and u with b1 bits, of the non-equilibrium stress with
+// b2 bits), packed low bit first into ceil((4 b1 + 6 b2)/32) words per cell.
+enum Format { FMT_F32 = 0, FMT_Q16 = 1, FMT_P16_15 = 2, FMT_P15_14 = 3, FMT_P14_13 = 4, FMT_P13_12 = 5, FMT_P12_11 = 6 };
+constexpr int kNumFormats = 7;
+
+// Bits of the rho / u codes and of the stress codes, and words per cell.
+constexpr int fmt_b1(int f) { return f == FMT_Q16 ? 16 : f == FMT_P16_15 ? 16 : f == FMT_P15_14 ? 15 : f == FMT_P14_13 ? 14 : f == FMT_P13_12 ? 13 : f == FMT_P12_11 ? 12 : 0; }
+constexpr int fmt_b2(int f) { return f == FMT_Q16 ? 16 : f == FMT_P16_15 ? 15 : f == FMT_P15_14 ? 14 : f == FMT_P14_13 ? 13 : f == FMT_P13_12 ? 12 : f == FMT_P12_11 ? 11 : 0; }
+constexpr int fmt_words(int f) { return f == FMT_F32 ? 10 : (4 * fmt_b1(f) + 6 * fmt_b2(f) + 31) / 32; }
+constexpr bool fmt_packed(int f) { return f >= FMT_P16_15 && f < kNumFormats; }
 
 // Boundary-list entry flags (bits 0..26 mark links i whose source x - c_i is solid).
 constexpr uint32_t BIT_INFLOW = 1u << 27;   // cell on the inflow face x = 0

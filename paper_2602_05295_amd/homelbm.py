@@ -18,6 +18,27 @@ LIB_PATH = os.path.join(PKG, "libhomelbm.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "homelbm.h")
 
 FP32, Q16 = 0, 1
+# b_rho_u / b_S bit allocations (codes of rho and u with b1 bits, of N with b2)
+PACKED = {"p16_15": (2, 16, 15), "p15_14": (3, 15, 14), "p14_13": (4, 14, 13), "p13_12": (5, 13, 12),
+          "p12_11": (6, 12, 11)}
+FORMATS = {"fp32": FP32, "q16": Q16, **{k: v[0] for k, v in PACKED.items()}}
+BITS = {Q16: (16, 16), **{v[0]: (v[1], v[2]) for v in PACKED.values()}}
+
+
+def raw_planes(fmt: int) -> int:
+    """Planes of the raw state: 10 floats, or ceil((4 b1 + 6 b2)/32) words."""
+    if fmt == FP32:
+        return 10
+    b1, b2 = BITS[fmt]
+    return (4 * b1 + 6 * b2 + 31) // 32
+
+
+def _fmt_code(fmt):
+    if isinstance(fmt, str):
+        return FORMATS[fmt]
+    if int(fmt) in BITS or int(fmt) == FP32:
+        return int(fmt)
+    raise KeyError(fmt)
 DITHER_OFF, DITHER_PER_STEP, DITHER_STATIC = 0, 1, 2
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED, ERR_UNSTABLE = range(6)
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "UNSUPPORTED", 5: "UNSTABLE"}
@@ -192,7 +213,7 @@ class HomeLBM:
         L = lib()
         self.dims = tuple(int(d) for d in dims)
         self.N = int(np.prod(self.dims))
-        self.fmt = {"fp32": FP32, "q16": Q16, FP32: FP32, Q16: Q16}[fmt]
+        self.fmt = _fmt_code(fmt)
         d = (ctypes.c_int * 3)(*self.dims)
         self._mask = None
         mp = None
@@ -305,8 +326,9 @@ class HomeLBM:
         return int(lib().lbm_raw_bytes(self._h))
 
     def get_raw(self, out=None):
-        """Raw state: FP32 (10, nz, ny, nx) float32, Q16 (5, nz, ny, nx) uint32."""
-        shape, dt = ((10,) + self.dims[::-1], np.float32) if self.fmt == FP32 else ((5,) + self.dims[::-1], np.uint32)
+        """Raw state: FP32 (10, nz, ny, nx) float32, integer formats (W, nz, ny, nx) uint32."""
+        shape = (raw_planes(self.fmt),) + self.dims[::-1]
+        dt = np.float32 if self.fmt == FP32 else np.uint32
         if out is None:
             out = np.empty(shape, dtype=dt)
         p, dev, keep = _ptr(out, dt, int(np.prod(shape)))
@@ -315,7 +337,7 @@ class HomeLBM:
 
     def set_raw(self, raw):
         dt = np.float32 if self.fmt == FP32 else np.uint32
-        n = (10 if self.fmt == FP32 else 5) * self.N
+        n = raw_planes(self.fmt) * self.N
         p, dev, keep = _ptr(raw, dt, n)
         self._check(lib().lbm_set_raw(self._h, p, self.raw_bytes(), dev))
 
@@ -327,7 +349,7 @@ class HomeLBM:
         """One step from the raw state raw_in to raw_out (device tensors in the
         get_raw layout); the context's own state is left as it is."""
         dt = np.float32 if self.fmt == FP32 else np.uint32
-        n = (10 if self.fmt == FP32 else 5) * self.N
+        n = raw_planes(self.fmt) * self.N
         p1, d1, k1 = _ptr(raw_in, dt, n)
         p2, d2, k2 = _ptr(raw_out, dt, n)
         if not (d1 and d2):
@@ -431,7 +453,7 @@ class HomeLBMBatch:
         self.count = len(self.dims)
         if len(taus) != self.count:
             raise ValueError("one tau per domain")
-        self.fmt = {"fp32": FP32, "q16": Q16, FP32: FP32, Q16: Q16}[fmt]
+        self.fmt = _fmt_code(fmt)
         self.taus = [float(t) for t in taus]
         flat = (ctypes.c_int * (3 * self.count))(*[v for d in self.dims for v in d])
         tau_arr = (ctypes.c_double * self.count)(*self.taus)

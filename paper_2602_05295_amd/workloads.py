@@ -8,8 +8,9 @@ shape (nz, ny, nx), vector fields (3, nz, ny, nx), moment fields
 (10, nz, ny, nx).
 
 The shapes and distributions stand in for the paper's scenes (Sec. 6): a
-Taylor-Green vortex, decaying turbulence in a periodic box, a channel with
-many obstacles, many small domains, and a box with spheres.
+Taylor-Green vortex, decaying turbulence in a periodic box, a double shear
+layer (the bit-allocation study), a channel with many obstacles, many small
+domains, and a box with spheres.
 """
 from __future__ import annotations
 
@@ -38,6 +39,25 @@ def taylor_green_2d(nx: int, ny: int, nz: int, U0: float = 0.05):
     uz = np.zeros_like(ux)
     rho = 1.0 - 0.75 * U0 * U0 * (np.cos(2 * k * x) + np.cos(2 * k * y)) + z
     return rho, np.stack([ux, uy, uz])
+
+
+def double_shear_layer(nx: int, ny: int, nz: int, U0: float = 0.04, width: float = 1.0 / 80.0,
+                       amp: float = 0.05, zamp: float = 0.02, seed: int = 0):
+    """A 3D analogue of the double-layer vortex: two periodic shear layers,
+    u_x = U0 tanh((y/ny - 1/4)/width) below y = ny/2 and
+    U0 tanh((3/4 - y/ny)/width) above, perturbed by
+    u_y = amp U0 sin(2 pi (x/nx + 1/4)) and a small seeded random z
+    modulation of that perturbation (so the roll-up is three-dimensional);
+    rho = 1.  Returns (rho, u)."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    yy = (y + 0.5) / ny
+    ux = np.where(yy <= 0.5, np.tanh((yy - 0.25) / width), np.tanh((0.75 - yy) / width))
+    phase = rng.uniform(0, 2 * np.pi, 2)
+    mod = 1.0 + zamp / amp * 0.5 * (np.sin(2 * np.pi * z / nz + phase[0]) + np.sin(4 * np.pi * z / nz + phase[1]))
+    uy = amp * np.sin(2 * np.pi * (x / nx + 0.25)) * mod
+    u = np.stack([U0 * ux, U0 * uy, np.zeros_like(ux)])
+    return np.ones((nz, ny, nx)), u
 
 
 def random_solenoidal(nx: int, ny: int, nz: int, kmax: float, umax: float, seed: int = 0):

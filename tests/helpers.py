@@ -35,3 +35,25 @@ def unpack(w):
 
 def fluid(mask, shape):
     return np.ones(shape[1:], bool) if mask is None else (mask == 0)
+
+
+def unpack_packed(w, b1, b2):
+    """Codes of the b1 / b2 packed layout (rho, ux, uy, uz with b1 bits, N
+    with b2 bits, concatenated low bit first across a cell's words)."""
+    w = np.asarray(w, dtype=np.uint64)
+    out = np.empty((10,) + w.shape[1:], dtype=np.int64)
+    o = 0
+    for k in range(10):
+        b = b1 if k < 4 else b2
+        i, s = divmod(o, 32)
+        v = w[i] >> np.uint64(s)
+        if s + b > 32:
+            v = v | (w[i + 1] << np.uint64(32 - s))
+        out[k] = (v & np.uint64((1 << b) - 1)).astype(np.int64)
+        o += b
+    return out
+
+
+def delta_bits(b1, b2):
+    """Quantization steps of (rho, u, N) with b1 / b2 bits."""
+    return np.array([0.7 / (2 ** b1 - 1)] + [0.8 / (2 ** b1 - 1)] * 3 + [0.2 / (2 ** b2 - 1)] * 6)

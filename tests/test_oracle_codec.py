@@ -250,3 +250,25 @@ def test_packed_round_trip_error(orc, b1, b2):
         r = cvars(orc.qb_decode(orc.qb_encode(m, b1, b2, t=1, seed=5, mode=mode), b1, b2))
         err = np.abs(r - v).reshape(10, -1).max(axis=1)
         assert np.all(err <= bound * d * (1 + 1e-3) + 1e-7), (mode, err / d)
+
+
+def test_exact_ties_round_to_even(orc):
+    """Reading R15: the encode decision, taken in single precision, sends an
+    exact tie (m - min) s = n + 1/2 to the even neighbour, so that ties add
+    no systematic drift.  Inputs with exact ties are found by searching
+    floats near min + (n + 1/2)/s."""
+    k = 1  # u_x: min = -0.4, 65535 / 0.8 per unit
+    lo = np.float32(orc.Q_LO[k])
+    s = np.float32(65535.0 / (orc.Q_HI[k] - orc.Q_LO[k]))
+    found = {0: 0, 1: 0}
+    for n in range(20000, 20400):
+        m = np.float32(lo + np.float32((n + 0.5) / float(s)))
+        for _ in range(64):
+            y = np.float32(np.float32(m - lo) * s)
+            if y == n + 0.5:
+                want = n if n % 2 == 0 else n + 1
+                assert orc.encode_one(float(m), k) == want, (n, float(m))
+                found[n % 2] += 1
+                break
+            m = np.nextafter(m, np.float32(np.inf) if y < n + 0.5 else np.float32(-np.inf))
+    assert found[0] > 0 and found[1] > 0, found
