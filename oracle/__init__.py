@@ -90,6 +90,10 @@ def lib():
         L.orc_post_collision_f.argtypes = [_P(Params), _dp, _dp, _dp, _dp]
         L.orc_step.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int]
         L.orc_object_forces.argtypes = [_P(Params), _u8, _dp, _dp]
+        L.orc_stream_post.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int]
+        L.orc_collide_field.argtypes = [_P(Params), _u8, _dp, _dp]
+        L.orc_mixed_q16_step.argtypes = [_P(Params), _u8, _u32, _u32, _dp, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_int, ctypes.c_int]
         L.orc_qb_encode.argtypes = [_dp, _u8, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, _u32]
         L.orc_qb_decode.argtypes = [_u32, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _dp]
@@ -201,6 +205,37 @@ def step(params: Params, m, mask=None, nthreads=None):
     mk, mp = _mask_ptr(mask)
     lib().orc_step(ctypes.byref(params), mp, _ptr(m, _dp), _ptr(out, _dp), nthreads or default_threads())
     return out
+
+
+def stream_post(params: Params, m_post, mask=None, nthreads=None):
+    """Post-stream moments from post-collision moments (the mixed pipeline's
+    stream pass, boundary rules included); solid cells get rest."""
+    m_post = _check_field(m_post, params, np.float64)
+    out = np.empty_like(m_post)
+    mk, mp = _mask_ptr(mask)
+    lib().orc_stream_post(ctypes.byref(params), mp, _ptr(m_post, _dp), _ptr(out, _dp), nthreads or default_threads())
+    return out
+
+
+def collide_field(params: Params, m, mask=None):
+    """Post-collision moments (rho, rho u+, rho S+) of every cell (App. A)."""
+    m = _check_field(m, params, np.float64)
+    out = np.empty_like(m)
+    mk, mp = _mask_ptr(mask)
+    lib().orc_collide_field(ctypes.byref(params), mp, _ptr(m, _dp), _ptr(out, _dp))
+    return out
+
+
+def mixed_q16_step(params: Params, w, mask=None, t=0, seed=0, mode=1, nthreads=None):
+    """One step of the mixed pipeline on 16-bit post-collision codes:
+    returns (codes of the new post-collision state, FP64 post-stream moments)."""
+    w = _check_field(w, params, np.uint32, 5)
+    out = np.empty_like(w)
+    m_ps = np.empty((10,) + w.shape[1:], np.float64)
+    mk, mp = _mask_ptr(mask)
+    lib().orc_mixed_q16_step(ctypes.byref(params), mp, _ptr(w, _u32), _ptr(out, _u32), _ptr(m_ps, _dp), t, seed, mode,
+                             nthreads or default_threads())
+    return out, m_ps
 
 
 def object_forces(params: Params, m, mask):

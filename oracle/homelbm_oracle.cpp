@@ -584,6 +584,72 @@ int orc_step(const OrcParams* P, const uint8_t* mask, const double* in, double* 
   return 0;
 }
 
+// ---- The paper's mixed-precision pipeline (Sec. 5.3, atomic accumulation):
+// the 16-bit buffer holds post-collision moments; a step streams them into
+// FP32 post-stream moments (the boundary rules applied), then collides and
+// re-encodes them.  Without quantization, stream(collide(m)) is the step of m.
+
+// Post-stream moments of every cell from post-collision moments m_post
+// (rho, rho u+, rho S+ per cell); solid cells get rest.
+int orc_stream_post(const OrcParams* P, const uint8_t* mask, const double* m_post, double* m_ps, int nthreads) {
+  Grid<double> G(*P, mask);
+  const int64_t N = G.N;
+  std::vector<Cell<double>> post(N);
+  for (int64_t c = 0; c < N; ++c) {
+    double m[10];
+    for (int k = 0; k < 10; ++k) m[k] = m_post[k * N + c];
+    post[c] = to_cell(m);
+  }
+  auto get = [&](int64_t c) -> const Cell<double>& { return post[c]; };
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+  for (int z = 0; z < P->nz; ++z)
+    for (int y = 0; y < P->ny; ++y)
+      for (int x = 0; x < P->nx; ++x) {
+        double m[10];
+        new_moments(G, x, y, z, get, m);
+        const int64_t c = G.idx(x, y, z);
+        for (int k = 0; k < 10; ++k) m_ps[k * N + c] = m[k];
+      }
+  return 0;
+}
+
+// Post-collision moments (rho, rho u+, rho S+) of every cell (App. A); solid
+// cells get rest.
+int orc_collide_field(const OrcParams* P, const uint8_t* mask, const double* m_ps, double* m_post) {
+  const int64_t N = int64_t(P->nx) * P->ny * P->nz;
+  for (int64_t c = 0; c < N; ++c) {
+    double out[10] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (!(mask && mask[c])) {
+      double m[10];
+      for (int k = 0; k < 10; ++k) m[k] = m_ps[k * N + c];
+      const Cell<double> q = collide(to_cell(m), P->F, P->tau);
+      out[0] = q.rho;
+      for (int a = 0; a < 3; ++a) out[1 + a] = q.rho * q.u[a];
+      for (int p = 0; p < 6; ++p) out[4 + p] = q.rho * q.S[PA[p]][PB[p]];
+    }
+    for (int k = 0; k < 10; ++k) m_post[k * N + c] = out[k];
+  }
+  return 0;
+}
+
+void orc_q16_encode(const double* m, const uint8_t* mask, int64_t N, uint32_t t, uint32_t seed, int mode,
+                    uint32_t* w);
+void orc_q16_decode(const uint32_t* w, int64_t N, double* m);
+
+// One step of the mixed pipeline on 16-bit post-collision codes: decode,
+// stream (m_ps receives the FP64 post-stream moments), collide, encode with
+// the dither of step t.
+int orc_mixed_q16_step(const OrcParams* P, const uint8_t* mask, const uint32_t* in, uint32_t* out, double* m_ps,
+                       uint32_t t, uint32_t seed, int mode, int nthreads) {
+  const int64_t N = int64_t(P->nx) * P->ny * P->nz;
+  std::vector<double> post(10 * N), post2(10 * N);
+  orc_q16_decode(in, N, post.data());
+  orc_stream_post(P, mask, post.data(), m_ps, nthreads);
+  orc_collide_field(P, mask, m_ps, post2.data());
+  orc_q16_encode(post2.data(), mask, N, t, seed, mode, out);
+  return 0;
+}
+
 // Force and torque on every object during the step from `in` (R17), summed
 // over the links of the fluid cells whose source is solid: out[6 id + 0..2]
 // force, out[6 id + 3..5] torque about the object's center, ids 0..255.

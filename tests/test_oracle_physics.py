@@ -296,3 +296,45 @@ def test_torque_moves_with_the_center(orc):
         np.testing.assert_allclose(f2[k, :3], f1[k, :3], rtol=1e-12, atol=1e-15)
         want = f1[k, 3:] + np.cross(obj1[k, :3] - obj2[k, :3], f1[k, :3])
         np.testing.assert_allclose(f2[k, 3:], want, rtol=1e-10, atol=1e-13)
+
+
+# --------------------------------------- the paper's mixed-precision pipeline ---
+# Storing post-collision instead of post-stream moments moves the storage
+# point by half a step: without quantization, stream(collide(m)) is the step.
+
+@pytest.mark.parametrize("case", ["periodic", "walls", "faces"])
+def test_mixed_pipeline_is_the_step_shifted(orc, case):
+    dims = (14, 11, 9)
+    mask, inflow, rule = None, False, 0
+    if case != "periodic":
+        mask = W.sphere_mask(*dims, phi=0.1, rmin=1.5, rmax=2.5, seed=3)
+    if case == "walls":
+        rule = 1
+    if case == "faces":
+        mask[:, :, :3] = 0
+        mask[:, :, -3:] = 0
+        inflow = True
+    P = orc.make_params(dims, 0.62, inflow=inflow, u_in=(0.05, 0.01, 0.0), wall_rule=rule)
+    m = W.random_moments(*dims, seed=7, dj=0.02, dp=0.003).astype(np.float64)
+    if mask is not None:
+        m[:, mask > 0] = np.array([1, 0, 0, 0, 0, 0, 0, 0, 0, 0])[:, None]
+    want = orc.step(P, m, mask)
+    got = orc.stream_post(P, orc.collide_field(P, m, mask), mask)
+    assert np.abs(got - want).max() < 1e-14
+
+
+def test_mixed_q16_step_keeps_rest_and_mass(orc):
+    dims = (10, 9, 8)
+    rest = orc.q16_encode(orc.equilibrium_moments(np.ones(dims[::-1]), np.zeros((3,) + dims[::-1])))
+    # the rest codes decode to N = +Delta/2 (reading R14); at tau = 1 the
+    # collision sets N to 0, whose code is the rest code again
+    out, m_ps = orc.mixed_q16_step(orc.make_params(dims, 1.0), rest, mode=0)
+    assert np.array_equal(out, rest)
+    P = orc.make_params(dims, 0.6)
+    # streaming moves mass and momentum without loss: the post-stream sums equal
+    # the decoded post-collision sums
+    w = orc.q16_encode(W.random_moments(*dims, seed=2, dj=0.02, dp=0.003))
+    post = orc.q16_decode(w)
+    out, m_ps = orc.mixed_q16_step(P, w, t=1, seed=3, mode=1)
+    for k in range(4):
+        assert abs(m_ps[k].sum() - post[k].sum()) < 1e-10 * max(1.0, abs(post[k].sum()))
