@@ -112,6 +112,19 @@ typedef struct lbm_options {
                          per link, torque about the object's center) to sums read by
                          lbm_get_object_forces; 0 (default): not computed.  Not supported
                          by batches. */
+  int pipeline;       /* 0 (default): the fluid pass keeps the unrounded moments of the
+                         listed cells and the boundary pass overwrites them (40 B of state
+                         traffic per cell and step).  1: the paper's mixed-precision pipeline
+                         (Sec. 5.3, atomic accumulation), for comparison: the 16-bit buffer
+                         holds post-collision moments; a step streams them into an FP32
+                         post-stream buffer, adds the changed links' corrections with
+                         atomicAdd and re-encodes (120 B per cell and step; 60 B of state
+                         per cell).  16-bit contexts without force or force tracking only
+                         (LBM_ERR_UNSUPPORTED).  lbm_get_raw returns the codes of the
+                         post-collision moments; lbm_set_raw, lbm_step_into and the adjoint
+                         are not supported.  lbm_get_moments returns the post-stream
+                         moments, as in pipeline 0.  Switching moves the current moments to
+                         the other storage. */
 } lbm_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -271,6 +284,14 @@ int lbm_synchronize(lbm_ctx* ctx);
  * passes and of the boundary passes, and the number of launches of each.
  * Synchronises.
  */
+/*
+ * Runs n steps like lbm_step, timing each stage with HIP events on the
+ * context stream: ms[0] the fluid (or stream) pass, ms[1] the boundary pass
+ * (or the link corrections), ms[2] the requantize pass of pipeline 1 (0
+ * otherwise); sums over the n steps.  Synchronises.
+ */
+int lbm_profile_stages(lbm_ctx* ctx, int n, double ms[3]);
+
 int lbm_profile_steps(lbm_ctx* ctx, int n, double* fluid_ms, double* boundary_ms, int* fluid_launches,
                       int* boundary_launches);
 

@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(ROOT, "_build", "homelbm")
 LIB = os.path.join(PKG, "libhomelbm.so")
 
 SOURCES = ["lbm_api.hip", "lbm_fluid.hip", "lbm_boundary.hip", "lbm_aux.hip", "lbm_adjoint.hip",
-           "lbm_batch.hip", "lbm_batch_api.hip"]
+           "lbm_batch.hip", "lbm_batch_api.hip", "lbm_mixed.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = "gfx950"

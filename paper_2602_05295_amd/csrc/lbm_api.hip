@@ -42,6 +42,12 @@ struct lbm_ctx {
   float h_objects[256 * 9] = {};      // per object id: center, velocity, angular velocity
   float* d_objects = nullptr;         // device copy of h_objects
   double* d_forces = nullptr;         // 256 x 6 force and torque sums (track_forces)
+  // the paper's mixed-precision pipeline (pipeline 1): buf[cur] holds the codes
+  // of post-collision moments, d_ps the FP32 post-stream moments
+  float* d_ps = nullptr;
+  uint32_t* d_links = nullptr;        // changed links, 32 e + i
+  int64_t n_links = 0;
+  bool links_built = false;
   bool flags_valid = false;
   bool list_built = false;
   int list_inflow = -1;
@@ -168,6 +174,7 @@ int build_list(lbm_ctx* c) {
   c->n_solid_b = cnt[1];
   c->list_built = true;
   c->list_inflow = g.inflow;
+  c->links_built = false;
   return LBM_OK;
 }
 
@@ -232,6 +239,113 @@ int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
   const int r = enqueue_pass(c, c->buf[c->cur], c->buf[1 - c->cur], ev);
   if (r == LBM_OK) c->cur = 1 - c->cur;
   return r;
+}
+
+// ---- the mixed pipeline
+void ps_planes(const lbm_ctx* c, void* pl[10]) {
+  for (int k = 0; k < 10; ++k) pl[k] = c->d_ps + size_t(k) * size_t(c->N);
+}
+
+int build_links(lbm_ctx* c) {
+  std::vector<uint32_t> hb(size_t(c->n_fluid_b));
+  hipError_t e = hipSuccess;
+  if (c->n_fluid_b > 0) e = hipMemcpy(hb.data(), c->d_bits, hb.size() * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the boundary list");
+  std::vector<uint32_t> links;
+  for (size_t k = 0; k < hb.size(); ++k) {
+    const uint32_t b = hb[k];
+    if (b & (BIT_INFLOW | BIT_OUTFLOW)) {
+      const int cx = (b & BIT_INFLOW) ? 1 : -1;
+      for (int cz = -1; cz <= 1; ++cz)
+        for (int cy = -1; cy <= 1; ++cy) links.push_back(uint32_t(k) * 32u + uint32_t((cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)));
+    } else {
+      for (uint32_t i = 0; i < 27; ++i)
+        if (i != 13 && ((b >> i) & 1u)) links.push_back(uint32_t(k) * 32u + i);
+    }
+  }
+  if (c->d_links) (void)hipFree(c->d_links);
+  c->d_links = nullptr;
+  c->n_links = int64_t(links.size());
+  if (!links.empty()) {
+    e = hipMalloc(&c->d_links, links.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(c->d_links, links.data(), links.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading the link list");
+  }
+  c->links_built = true;
+  return LBM_OK;
+}
+
+// Codes of collide(d_ps) into buf[cur], then the listed solid cells to rest.
+int mixed_requantize(lbm_ctx* c, bool dither, hipEvent_t ev0, hipEvent_t ev1) {
+  StepParams p = step_params(c, c->buf[c->cur], c->buf[c->cur]);
+  void* pl[10];
+  ps_planes(c, pl);
+  for (int k = 0; k < 10; ++k) p.in[k] = pl[k];
+  if (!dither) p.dither = 0;
+  hipError_t e = hipSuccess;
+  if (ev0) e = hipEventRecord(ev0, c->stream);
+  if (e == hipSuccess) e = launch_requantize(p, c->N, c->stream);
+  if (e == hipSuccess && c->n_solid_b > 0)
+    e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b),
+                        c->stream);
+  if (e == hipSuccess && ev1) e = hipEventRecord(ev1, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "requantize");
+  return LBM_OK;
+}
+
+// One step of the mixed pipeline: stream pass, link corrections, requantize.
+int enqueue_mixed_step(lbm_ctx* c, hipEvent_t ev[6]) {
+  if (!c->links_built) {
+    const int r = build_links(c);
+    if (r != LBM_OK) return r;
+  }
+  StepParams p = step_params(c, c->buf[c->cur], c->buf[c->cur]);
+  void* pl[10];
+  ps_planes(c, pl);
+  for (int k = 0; k < 10; ++k) p.out[k] = pl[k];
+  p.lc = ListedCells{};
+  hipError_t e = hipSuccess;
+  if (ev) e = hipEventRecord(ev[0], c->stream);
+  if (e == hipSuccess) e = launch_stream_mixed(p, c->opt.tile_rows, c->stream);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], c->stream);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[2], c->stream);
+  if (e == hipSuccess)
+    e = launch_mixed_links(p, c->d_links, int(c->n_links), c->d_cells, c->d_yz, c->d_bits, c->stream);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mixed stream pass");
+  const int r = mixed_requantize(c, true, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr);
+  if (r != LBM_OK) return r;
+  c->t += 1;
+  return LBM_OK;
+}
+
+// Moves the state between the two pipelines (same moments, other storage).
+int switch_pipeline(lbm_ctx* c, int to) {
+  hipError_t e = hipSuccess;
+  if (!c->d_ps) {
+    e = hipMalloc(&c->d_ps, size_t(c->N) * 40);
+    if (e != hipSuccess) return hip_fail(c, e, "allocating the FP32 post-stream buffer");
+  }
+  void* pl[10];
+  ps_planes(c, pl);
+  const void* cpl[10];
+  for (int k = 0; k < 10; ++k) cpl[k] = pl[k];
+  void* qpl[10];
+  planes_of(c, c->buf[c->cur], qpl);
+  const void* cqpl[10];
+  for (int k = 0; k < 10; ++k) cqpl[k] = qpl[k];
+  if (to == 1) {
+    // codes of pre-collision moments -> full moments in d_ps -> FP32 state layout (in place) -> requantize
+    e = launch_get_moments(c->fmt, cqpl, c->d_ps, c->d_mask, c->N, c->stream);
+    if (e == hipSuccess) e = launch_set_moments(FMT_F32, c->d_ps, pl, c->d_mask, c->N, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "entering the mixed pipeline");
+    return mixed_requantize(c, false, nullptr, nullptr);
+  }
+  // FP32 post-stream moments -> full moments (in place) -> codes of pre-collision moments
+  e = launch_get_moments(FMT_F32, cpl, c->d_ps, c->d_mask, c->N, c->stream);
+  if (e == hipSuccess) e = launch_set_moments(c->fmt, c->d_ps, qpl, c->d_mask, c->N, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "leaving the mixed pipeline");
+  return LBM_OK;
 }
 
 int scan_health(lbm_ctx* c, uint64_t* bad) {
@@ -338,6 +452,8 @@ int lbm_destroy(lbm_ctx* c) {
   if (c->d_flags) (void)hipFree(c->d_flags);
   if (c->d_objects) (void)hipFree(c->d_objects);
   if (c->d_forces) (void)hipFree(c->d_forces);
+  if (c->d_ps) (void)hipFree(c->d_ps);
+  if (c->d_links) (void)hipFree(c->d_links);
   delete c;
   return LBM_OK;
 }
@@ -358,6 +474,10 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
     if (!std::isfinite(o->force[a]) || std::fabs(o->force[a]) > 0.01f)
       return fail(c, LBM_ERR_INVALID_ARG, "force must be finite with |F_a| <= 0.01");
   if (o->wall_rule != 0 && o->wall_rule != 1) return fail(c, LBM_ERR_INVALID_ARG, "wall_rule must be 0 or 1");
+  if (o->pipeline != 0 && o->pipeline != 1) return fail(c, LBM_ERR_INVALID_ARG, "pipeline must be 0 or 1");
+  if (o->pipeline == 1 && (c->fmt != FMT_Q16 || o->force[0] != 0.0f || o->force[1] != 0.0f ||
+                           o->force[2] != 0.0f || o->track_forces != 0))
+    return fail(c, LBM_ERR_UNSUPPORTED, "the mixed pipeline runs 16-bit contexts without body force or force tracking");
   if (o->track_forces != 0 && o->track_forces != 1) return fail(c, LBM_ERR_INVALID_ARG, "track_forces must be 0 or 1");
   int r = check_faces(c, *o);
   if (r != LBM_OK) return r;
@@ -373,11 +493,17 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
         return fail(c, LBM_ERR_INVALID_ARG, "solid cells within two cells of an open x face");
     }
   }
-  const int old_inflow = c->opt.inflow;
+  const int old_inflow = c->opt.inflow, old_pipeline = c->opt.pipeline;
   c->opt = *o;
+  c->opt.pipeline = old_pipeline;
   if (!c->list_built || old_inflow != o->inflow) {
     r = build_list(c);
     if (r != LBM_OK) return r;
+  }
+  if (o->pipeline != old_pipeline) {
+    r = switch_pipeline(c, o->pipeline);
+    if (r != LBM_OK) return r;
+    c->opt.pipeline = o->pipeline;
   }
   return LBM_OK;
 }
@@ -409,7 +535,11 @@ int lbm_set_moments(lbm_ctx* c, const float* m, int on_device) {
   if (r != LBM_OK) return r;
   void* pl[10];
   planes_of(c, c->buf[c->cur], pl);
-  hipError_t e = launch_set_moments(c->fmt, static_cast<const float*>(dm), pl, c->d_mask, c->N, c->stream);
+  const bool mixed = c->opt.pipeline == 1;
+  if (mixed) ps_planes(c, pl);
+  hipError_t e = launch_set_moments(mixed ? int(FMT_F32) : c->fmt, static_cast<const float*>(dm), pl, c->d_mask, c->N,
+                                    c->stream);
+  if (e == hipSuccess && mixed && mixed_requantize(c, false, nullptr, nullptr) != LBM_OK) e = hipErrorUnknown;
   if (e == hipSuccess && owned) e = hipStreamSynchronize(c->stream);
   if (owned) (void)hipFree(dm);
   if (e != hipSuccess) return hip_fail(c, e, "set_moments");
@@ -429,8 +559,11 @@ int lbm_set_equilibrium(lbm_ctx* c, const float* rho, const float* u, int on_dev
   }
   void* pl[10];
   planes_of(c, c->buf[c->cur], pl);
-  hipError_t e = launch_set_equilibrium(c->fmt, static_cast<const float*>(dr), static_cast<const float*>(du), pl,
-                                        c->d_mask, c->N, c->stream);
+  const bool mixed = c->opt.pipeline == 1;
+  if (mixed) ps_planes(c, pl);
+  hipError_t e = launch_set_equilibrium(mixed ? int(FMT_F32) : c->fmt, static_cast<const float*>(dr),
+                                        static_cast<const float*>(du), pl, c->d_mask, c->N, c->stream);
+  if (e == hipSuccess && mixed && mixed_requantize(c, false, nullptr, nullptr) != LBM_OK) e = hipErrorUnknown;
   if (e == hipSuccess && (o1 || o2)) e = hipStreamSynchronize(c->stream);
   if (o1) (void)hipFree(dr);
   if (o2) (void)hipFree(du);
@@ -446,7 +579,7 @@ int lbm_step(lbm_ctx* c, int n) {
     if (r != LBM_OK) return r;
   }
   for (int s = 0; s < n; ++s) {
-    const int r = enqueue_step(c, nullptr);
+    const int r = c->opt.pipeline == 1 ? enqueue_mixed_step(c, nullptr) : enqueue_step(c, nullptr);
     if (r != LBM_OK) return r;
   }
   if (c->opt.check_health && n > 0) {
@@ -494,6 +627,7 @@ int lbm_get_object_forces(lbm_ctx* c, double* out, int reset) {
 int lbm_step_into(lbm_ctx* c, const void* in, void* out) {
   if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
   if (!in || !out) return fail(c, LBM_ERR_INVALID_ARG, "NULL state buffer");
+  if (c->opt.pipeline == 1) return fail(c, LBM_ERR_UNSUPPORTED, "the mixed pipeline has no lbm_step_into");
   const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
   const uintptr_t n = state_bytes(c);
   if (a < b + n && b < a + n) return fail(c, LBM_ERR_INVALID_ARG, "in and out overlap");
@@ -512,9 +646,11 @@ int lbm_get_moments(lbm_ctx* c, float* m, int on_device) {
   if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(get_moments staging)");
   void* pl[10];
   planes_of(c, c->buf[c->cur], pl);
+  const bool mixed = c->opt.pipeline == 1;
+  if (mixed) ps_planes(c, pl);
   const void* cpl[10];
   for (int k = 0; k < 10; ++k) cpl[k] = pl[k];
-  e = launch_get_moments(c->fmt, cpl, dm, c->d_mask, c->N, c->stream);
+  e = launch_get_moments(mixed ? int(FMT_F32) : c->fmt, cpl, dm, c->d_mask, c->N, c->stream);
   if (e == hipSuccess && !on_device) e = hipMemcpyAsync(m, dm, size_t(c->N) * 40, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
   if (!on_device) (void)hipFree(dm);
@@ -536,6 +672,7 @@ int lbm_get_raw(lbm_ctx* c, void* out, size_t bytes, int on_device) {
 
 int lbm_set_raw(lbm_ctx* c, const void* in, size_t bytes, int on_device) {
   if (!c || !in) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
+  if (c->opt.pipeline == 1) return fail(c, LBM_ERR_UNSUPPORTED, "the mixed pipeline has no raw states");
   if (bytes != state_bytes(c)) return fail(c, LBM_ERR_INVALID_ARG, "bytes must equal lbm_raw_bytes()");
   hipError_t e = hipMemcpyAsync(c->buf[c->cur], in, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                 c->stream);
@@ -571,7 +708,7 @@ int lbm_memory_bytes(const lbm_ctx* c, size_t* sb, size_t* tb) {
   const size_t s = 2 * state_bytes(c);
   if (sb) *sb = s;
   if (tb)
-    *tb = s + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 52 +
+    *tb = s + (c->d_ps ? size_t(c->N) * 40 : 0) + size_t(c->n_links) * 4 + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 52 +
           (c->d_lmask ? size_t((c->N + 63) / 64) * 28 : 0) + 4 * 4 + 8;
   return LBM_OK;
 }
@@ -596,35 +733,44 @@ int lbm_synchronize(lbm_ctx* c) {
   return e == hipSuccess ? LBM_OK : hip_fail(c, e, "hipStreamSynchronize");
 }
 
-int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, int* nf, int* nb) {
-  if (!c || n < 0) return fail(c, LBM_ERR_INVALID_ARG, "bad argument");
+int lbm_profile_stages(lbm_ctx* c, int n, double ms[3]) {
+  if (!c || n < 0 || !ms) return fail(c, LBM_ERR_INVALID_ARG, "bad argument");
   if (!c->list_built) {
     const int r = build_list(c);
     if (r != LBM_OK) return r;
   }
-  const bool has_b = (c->n_fluid_b + c->n_solid_b) > 0;
-  std::vector<hipEvent_t> ev(size_t(4) * n);
+  const bool mixed = c->opt.pipeline == 1;
+  const bool has_b = mixed || (c->n_fluid_b + c->n_solid_b) > 0;
+  std::vector<hipEvent_t> ev(size_t(6) * n);
   hipError_t e = hipSuccess;
   for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
   if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
   int r = LBM_OK;
-  for (int s = 0; s < n && r == LBM_OK; ++s) r = enqueue_step(c, &ev[size_t(4) * s]);
+  for (int s = 0; s < n && r == LBM_OK; ++s)
+    r = mixed ? enqueue_mixed_step(c, &ev[size_t(6) * s]) : enqueue_step(c, &ev[size_t(6) * s]);
   if (r == LBM_OK) e = hipStreamSynchronize(c->stream);
-  double tf = 0, tb = 0;
+  double t[3] = {0, 0, 0};
   for (int s = 0; s < n && r == LBM_OK && e == hipSuccess; ++s) {
-    float ms = 0;
-    e = hipEventElapsedTime(&ms, ev[size_t(4) * s], ev[size_t(4) * s + 1]);
-    tf += ms;
-    if (has_b && e == hipSuccess) {
-      e = hipEventElapsedTime(&ms, ev[size_t(4) * s + 2], ev[size_t(4) * s + 3]);
-      tb += ms;
+    for (int st = 0; st < (mixed ? 3 : (has_b ? 2 : 1)) && e == hipSuccess; ++st) {
+      float m = 0;
+      e = hipEventElapsedTime(&m, ev[size_t(6) * s + 2 * st], ev[size_t(6) * s + 2 * st + 1]);
+      t[st] += m;
     }
   }
   for (auto& x : ev) (void)hipEventDestroy(x);
   if (r != LBM_OK) return r;
   if (e != hipSuccess) return hip_fail(c, e, "profiling events");
-  if (fluid_ms) *fluid_ms = tf;
-  if (boundary_ms) *boundary_ms = tb;
+  for (int st = 0; st < 3; ++st) ms[st] = t[st];
+  return LBM_OK;
+}
+
+int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, int* nf, int* nb) {
+  double ms[3] = {0, 0, 0};
+  const int r = lbm_profile_stages(c, n, ms);
+  if (r != LBM_OK) return r;
+  const bool has_b = c->opt.pipeline == 1 || (c->n_fluid_b + c->n_solid_b) > 0;
+  if (fluid_ms) *fluid_ms = ms[0];
+  if (boundary_ms) *boundary_ms = ms[1] + ms[2];
   if (nf) *nf = n;
   if (nb) *nb = has_b ? n : 0;
   return LBM_OK;

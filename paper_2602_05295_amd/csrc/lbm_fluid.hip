@@ -117,8 +117,12 @@ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v -
 
 // FORCE: App. A with the uniform body force a.hF = F/2 (collision terms, and
 // F/2 added to the projected momentum, Eq. rho_u_stress).
-template <int FMT, int TYR, bool FORCE>
+// MIXED: the stream pass of the paper's mixed-precision pipeline (Sec. 5.3):
+// the codes hold post-collision moments, which are reconstructed without a
+// collision, and the new moments are stored as FP32 post-stream moments.
+template <int FMT, int TYR, bool FORCE, bool MIXED = false>
 __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg) {
+  constexpr int OUT = MIXED ? int(FMT_F32) : FMT;
   constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
   __shared__ FluidLds<TYR> L;
 
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     Raw<FMT> bufB;
     // listed cells to look for: a wavefront-uniform condition, so that the
     // bitmap words stay in scalar registers and empty words skip everything
-    const bool keep = compute && a.lc.side != nullptr;
+    const bool keep = !MIXED && compute && a.lc.side != nullptr;
     const uint32_t row0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: the row's first own cell
     ListedPair lwA{}, lwB{};
     // New moments of the plane finished by the previous step.  They are
@@ -178,7 +182,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     auto store_plane = [&](int ps, const ListedPair& lw) {
       if (own) {
         const uint32_t cell = row + plane * uint32_t(ps);
-        store_cell<FMT>(a, cell, sdr, sj, sP);
+        store_cell<OUT>(a, cell, sdr, sj, sP);
         if (keep && (lw.a.x | lw.a.y | lw.b.x | lw.b.y) != 0u) keep_listed(a.lc, cell, lw, sdr, sj, sP);
       }
     };
@@ -196,7 +200,10 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
 
       const CellIn c = decode<FMT>(cur);
       float A[NA];
-      post_collision<FORCE>(c, a.om1, a.hF, A);
+      if constexpr (MIXED)
+        hermite_coeffs(c.dr, c.j, c.u, c.N, A);  // the codes are post-collision already
+      else
+        post_collision<FORCE>(c, a.om1, a.hF, A);
 
       // ---- y pass: groups (n, l) with inputs m = 0, 1, 2 along y
       float f0[8], fp[8], fm[8];
@@ -346,20 +353,20 @@ int device_cus() {
   return cached[dev];
 }
 
-template <int FMT, bool FORCE>
+template <int FMT, bool FORCE, bool MIXED = false>
 hipError_t launch_rows(int rows, dim3 grid, const StepParams& p, int ntx, int nty, int nseg, int nwg, hipStream_t s) {
   switch (rows) {
     case 8:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE>), grid, dim3(11 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED>), grid, dim3(11 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
     case 10:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE>), grid, dim3(13 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED>), grid, dim3(13 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
     case 12:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE>), grid, dim3(15 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED>), grid, dim3(15 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
     default:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE>), grid, dim3(16 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED>), grid, dim3(16 * RW), 0, s, p, ntx, nty, nseg, nwg);
       break;
   }
   return hipGetLastError();
@@ -403,6 +410,12 @@ FluidPlan fluid_plan(const Geometry& g, int rows, int cus) {
     }
   }
   return best;
+}
+
+hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s) {
+  const FluidPlan c = fluid_plan(p.g, rows, device_cus());
+  if (c.rows == 0) return hipErrorInvalidValue;
+  return launch_rows<FMT_Q16, false, true>(c.rows, dim3(uint32_t(c.nwg)), p, c.ntx, c.nty, c.nseg, c.nwg, s);
 }
 
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {

@@ -137,6 +137,19 @@ extern const int kFluidTileRows[4];
 FluidPlan fluid_plan(const Geometry& g, int rows, int cus);
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s);
 
+// The paper's mixed-precision pipeline (Sec. 5.3, atomic accumulation), on
+// 16-bit codes of post-collision moments:
+//   stream pass: p.in = the codes, p.out = ten FP32 post-stream planes;
+//   link corrections: one thread per changed link (links[k] = 32 e + i, e a
+//     listed fluid entry, i its direction), atomicAdd of (new - pulled) times
+//     the link's moments into p.out (p.in still the codes);
+//   requantize: p.in = the FP32 planes, p.out = the codes: collide (App. A)
+//     and encode every cell with the dither of p.key.
+hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s);
+hipError_t launch_mixed_links(const StepParams& p, const uint32_t* links, int nlinks, const uint32_t* cells,
+                              const uint32_t* yz, const uint32_t* bits, hipStream_t s);
+hipError_t launch_requantize(const StepParams& p, int64_t N, hipStream_t s);
+
 // Boundary pass: the nfluid listed fluid cells (list order = slot order,
 // with their y | z << 16 in yz) take the fluid pass's moments from p.lc.side
 // and the corrections of their boundary links; then the nsolid listed solid

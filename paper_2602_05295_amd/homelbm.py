@@ -61,6 +61,7 @@ class Options(ctypes.Structure):
         ("force", ctypes.c_float * 3),
         ("wall_rule", ctypes.c_int),
         ("track_forces", ctypes.c_int),
+        ("pipeline", ctypes.c_int),
     ]
 
 
@@ -115,6 +116,7 @@ def lib():
     L.lbm_step_into.argtypes = [vp, vp, vp]
     L.lbm_set_object.argtypes = [vp, i, vp, vp, vp]
     L.lbm_get_object_forces.argtypes = [vp, vp, i]
+    L.lbm_profile_stages.argtypes = [vp, i, vp]
     L.lbm_get_moments.argtypes = [vp, vp, i]
     L.lbm_raw_bytes.argtypes = [vp]
     L.lbm_raw_bytes.restype = sz
@@ -266,7 +268,7 @@ class HomeLBM:
         return o
 
     def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None, tile_rows=None,
-                    force=None, wall_rule=None, track_forces=None):
+                    force=None, wall_rule=None, track_forces=None, pipeline=None):
         o = self.options()
         if dither_mode is not None:
             o.dither_mode = int(dither_mode)
@@ -286,12 +288,21 @@ class HomeLBM:
             o.wall_rule = int(wall_rule)
         if track_forces is not None:
             o.track_forces = int(bool(track_forces))
+        if pipeline is not None:
+            o.pipeline = int(pipeline)
         self._check(lib().lbm_set_options(self._h, ctypes.byref(o)))
 
     def set_object(self, oid, center=(0.0, 0.0, 0.0), velocity=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0)):
         """Wall motion of solid object oid (its mask value) and its torque center."""
         f3 = lambda v: (ctypes.c_float * 3)(*[float(x) for x in v])
         self._check(lib().lbm_set_object(self._h, int(oid), f3(center), f3(velocity), f3(omega)))
+
+    def profile_stages(self, n):
+        """Runs n steps; summed device ms of the fluid / stream pass, the boundary
+        pass / link corrections, and the requantize pass (pipeline 1)."""
+        ms = np.zeros(3, np.float64)
+        self._check(lib().lbm_profile_stages(self._h, int(n), ms.ctypes.data_as(ctypes.c_void_p)))
+        return {"fluid_ms": ms[0], "boundary_ms": ms[1], "requantize_ms": ms[2], "steps": int(n)}
 
     def object_forces(self, reset=False):
         """(256, 6) sums of force and torque per object id since the last reset."""

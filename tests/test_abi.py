@@ -25,7 +25,7 @@ def test_options_struct_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"(\w+)\s+(\w+)(\[\d+\])?;", body)
     assert [f[1] for f in fields] == [f[0] for f in homelbm.Options._fields_]
-    assert ctypes.sizeof(homelbm.Options) == 4 * 13
+    assert ctypes.sizeof(homelbm.Options) == 4 * 14
 
 
 def test_default_options_without_gpu():
