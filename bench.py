@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 N = 256
 TAU = 0.51
 BYTES_PER_CELL = {"q16": 40, "fp32": 80}   # one state read + one state written
-KERNEL_SOURCES = ["paper_2602_05295_amd/csrc/lbm_fluid.hip", "paper_2602_05295_amd/csrc/lbm_device.h"]
+KERNEL_SOURCES = ["paper_2602_05295_amd/csrc/lbm_fluid.hip", "paper_2602_05295_amd/csrc/lbm_device.h",
+                  "paper_2602_05295_amd/csrc/lbm_codec.h", "paper_2602_05295_amd/csrc/lbm_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fluid_256cubed_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "fluid_256cubed_valu.json")
 VALU_PEAK_G = 256 * 4 * 2.4 / 4  # G wave64 VALU instructions per second
