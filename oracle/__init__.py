@@ -10,6 +10,10 @@ Fields are numpy arrays of shape (10, nz, ny, nx) (ten planes, x fastest) in
 the stored-moment order rho, jx, jy, jz, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz, with
 j = rho u and P = rho S (S the Hermite second moment of Eq. rho_u_stress).
 16-bit fields are uint32 arrays of shape (5, nz, ny, nx).
+
+Two numpy modules sit beside it, also test infrastructure: ``d2q9`` (the D2Q9
+models and amplification matrices of the paper's 2D von Neumann analysis) and
+``stability`` (the same analysis for the 3D step, and speed limits).
 """
 from __future__ import annotations
 

@@ -5,12 +5,16 @@ block circulant; its block Fourier transform must equal the 10x10 moment-space
 amplification matrix G(k) = sum_i exp(-i k.c_i) phi(c_i) d f+_i / d m, the
 moment form of Eq. (Mo-NOCM) for pull streaming.  G(0) has the closed-form
 spectrum {1 (x4), 0, 1 - 1/tau (x5)}; small-k modes follow Eqs. (shear_mode,
-acoustic_modes); and the von Neumann criterion max|lambda| <= 1 holds at
-u = 0."""
+acoustic_modes), the sound modes decaying with the bulk viscosity of App. A's
+trace reset; and the von Neumann criterion max|lambda| <= 1 holds at u = 0
+and at the drift speeds of the benchmark workloads."""
 import itertools
 
 import numpy as np
 import pytest
+
+import oracle as orc_mod
+from oracle import stability
 
 CS2 = 1.0 / 3.0
 H = 1e-30
@@ -122,3 +126,44 @@ def test_von_neumann_bound_at_rest(orc, tau):
     G = np.einsum("ki,ia,ib->kab", ph, PHI, J)        # (nk, 10, 10)
     lam = np.abs(np.linalg.eigvals(G)).max()
     assert lam <= 1 + 1e-12
+
+
+def test_sound_attenuation_follows_the_bulk_rate():
+    """App. A sets the trace of S to |u|^2 (bulk relaxation rate 1), so by
+    Eq. acoustic_modes with D = 3 the sound modes decay at
+    k^2 (2 nu / 3 + mu_v / 2), mu_v = (2/3) cs^2 (1 - 1/2) = 1/9."""
+    from oracle import d2q9
+    c, w, _ = orc_mod.lattice()
+    for tau in (0.53, 0.6):
+        nu = (tau - 0.5) / 3
+        k = 2 * np.pi / 64
+        lam = np.linalg.eigvals(stability.amplification_grid_3d(np.array([k, 0, 0]), tau, 1.0, [0, 0, 0]))
+        om = 1j * np.log(lam)
+        hydro = om[np.abs(om.real) < 0.2]
+        hydro = hydro[np.argsort(hydro.real)]
+        damp = k * k * (2 * nu / 3 + 0.5 * d2q9.bulk_viscosity(1.0, D=3))
+        for ac in (hydro[0], hydro[-1]):
+            assert abs(-ac.imag / damp - 1) < 0.01
+
+
+@pytest.mark.parametrize("tau", [0.51, 0.52, 0.6])
+def test_stable_at_the_workload_speeds(tau):
+    """The step is von Neumann stable (max |lambda| <= 1 on a 12^3 wave grid)
+    at drift speeds up to 0.12 along x, xy and xyz for the relaxation times
+    the benchmarks use (their largest speed is the channel's inflow, 0.08)."""
+    for dvec in ((1, 0, 0), (1, 1, 0), (1, 1, 1)):
+        u = 0.12 * np.array(dvec, float) / np.linalg.norm(dvec)
+        assert stability.max_growth(3, None, tau, u, 12) <= 1 + 1e-10
+
+
+def test_amplification_matches_the_cell_symbol():
+    """stability.amplification_grid_3d is the symbol checked against the full
+    Jacobian above."""
+    c, w, _ = orc_mod.lattice()
+    PHI = _phi(c)
+    tau = 0.57
+    u = [0.04, -0.02, 0.03]
+    k = np.array([0.4, -1.3, 2.2])
+    m0 = _uniform(orc_mod, 1.0, u)
+    J = _cell_jac(orc_mod, orc_mod.make_params((4, 4, 4), tau), m0)
+    assert np.abs(stability.amplification_grid_3d(k, tau, 1.0, u) - _G(c, PHI, J, k)).max() < 1e-14
