@@ -243,3 +243,25 @@ def test_nonlinear_growth_follows_the_linear_rate():
     for _ in range(steps):
         f = d.step("nocm", f, tau)
     assert abs(coeff(f) / start / np.abs(lam[j]) ** steps - 1) < 1e-3
+
+
+def test_study_tables_have_their_shapes():
+    """The study behind the reported tables runs and fills every entry
+    (coarse grids here)."""
+    s = d.study(nk=9, nk2=5)
+    assert len(s["margin"]) == 3 * len(d.MODELS) and all(v.shape == (9,) for v in s["margin"].values())
+    assert len(s["dissipation"]) == 4 * len(d.MODELS) and all(v.shape == (5, 5) for v in s["dissipation"].values())
+    for om in s["dispersion"].values():
+        assert om.shape == (8, 3) and np.all(np.abs(om[:, 1].real) < 1e-9)    # shear branch at rest
+        assert np.all(om[:, 2].real > 0) and np.all(om[:, 0].real < 0)
+
+
+def test_speed_limit_brackets_the_crossing():
+    """stability.speed_limit returns a speed that is stable while a slightly
+    larger one is not (2D HOME composite, nu = 1e-3, coarse wave grid)."""
+    from oracle import stability
+    tau = d.tau_of_nu(1e-3)
+    s = stability.speed_limit(2, "home", tau, (1, 0), 16, iters=8)
+    assert 0.0 < s < 0.6
+    assert stability.max_growth(2, "home", tau, (s, 0.0), 16) <= 1 + 1e-10
+    assert stability.max_growth(2, "home", tau, (s + 0.6 / 2 ** 8 * 1.01, 0.0), 16) > 1 + 1e-10
