@@ -299,11 +299,15 @@ int lbm_profile_steps(lbm_ctx* ctx, int n, double* fluid_ms, double* boundary_ms
  * Host-only: the fluid pass's work split for a grid, without touching the
  * device.  tile_rows as in lbm_options; cus = compute units of the device.
  * out = {tile rows, tiles along x (64 cells each), tiles along y, z segments
- * per tile, workgroups launched}.  Work item q (0 <= q < tiles * segments)
- * is tile q % tiles in z segment q / tiles; workgroup w takes items w, w +
- * workgroups, ...  Errors: LBM_ERR_INVALID_ARG.
+ * per tile, workgroups launched, tail planes, tail workgroups}.  The z range
+ * below the tail, [0, nz - tail), is cut into the segments: work item q
+ * (0 <= q < tiles * segments) is tile q % tiles in z segment q / tiles, and
+ * the first workgroups - tail workgroups workgroups take items w, w + that
+ * count, ...  When the tail is not empty, tail workgroup j takes z in
+ * [nz - tail, nz) of tiles [tiles j / n, tiles (j + 1) / n), n the tail
+ * workgroups.  Errors: LBM_ERR_INVALID_ARG.
  */
-int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[5]);
+int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[7]);
 
 /*
  * Device-side dither generator, for known-answer tests: for each of the n

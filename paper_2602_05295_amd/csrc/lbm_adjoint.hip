@@ -456,7 +456,7 @@ hipError_t launch_adjoint(const AdjParams& p, int rows, const uint32_t* cells, c
                           hipStream_t s) {
   // the forward pass's split at one of the two compiled tile heights (8 unless
   // 13 is asked for: the 13-row tile needs more registers than fit)
-  const FluidPlan c = fluid_plan(p.g, rows == 13 ? 13 : 8, cus());
+  const FluidPlan c = fluid_plan(p.g, rows == 13 ? 13 : 8, cus(), /*allow_tail=*/false);
   if (c.rows == 8)
     hipLaunchKernelGGL(adjoint_fluid_kernel<8>, dim3(uint32_t(c.nwg)), dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                        c.nwg);

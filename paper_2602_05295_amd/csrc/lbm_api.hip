@@ -822,7 +822,7 @@ int lbm_equilibrium_vjp(lbm_ctx* c, const float* rho, const float* u, const floa
   return LBM_OK;
 }
 
-int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[5]) {
+int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[7]) {
   if (!dims || !out || cus < 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "bad argument");
   for (int a = 0; a < 3; ++a)
     if (dims[a] < 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "every dimension must be >= 1");
@@ -835,6 +835,8 @@ int lbm_fluid_plan(const int dims[3], int tile_rows, int cus, int out[5]) {
   out[2] = p.nty;
   out[3] = p.nseg;
   out[4] = p.nwg;
+  out[5] = p.tail;
+  out[6] = p.ntail;
   return LBM_OK;
 }
 

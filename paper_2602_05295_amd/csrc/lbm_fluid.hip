@@ -21,7 +21,9 @@
 //
 // Work items are (tile, z segment) pairs.  Every tile's z range is cut into
 // the same S equal segments, so all items of a wave start on the same plane
-// and advance in step: a tile's halo rows and columns are then read while the
+// and advance in step (when those items leave CUs idle, the top planes of
+// every tile are cut off first and shared out to the idle CUs, each taking a
+// run of tiles, so that both kinds of workgroup finish together): a tile's halo rows and columns are then read while the
 // neighbouring tile that owns them holds the same planes in L2.  Items are
 // numbered segment-major, tile-minor (x fastest) and the workgroups of one
 // XCD (round-robin dispatch) take consecutive numbers, so each XCD works on a
@@ -121,7 +123,7 @@ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v -
 // the codes hold post-collision moments, which are reconstructed without a
 // collision, and the new moments are stored as FP32 post-stream moments.
 template <int FMT, int TYR, bool FORCE, bool MIXED = false>
-__global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg) {
+__global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg, int zt, int ntail) {
   constexpr int OUT = MIXED ? int(FMT_F32) : FMT;
   constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
   __shared__ FluidLds<TYR> L;
@@ -145,13 +147,29 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
   const bool compute = !colw && inner;    // a row wavefront with outputs
 
   const int ntiles = ntx * nty;
-  const int items = ntiles * nseg;
+  const int items = ntiles * nseg;  // regular items: z in [0, zt)
+  const int nreg = nwg - ntail;     // their workgroups; the rest take z in [zt, nz)
   const uint32_t plane = uint32_t(nx) * uint32_t(ny);
+  const int k = xcd_logical_block(int(blockIdx.x), nwg);
+  const bool on_tail = k >= nreg;
+  const int t0 = on_tail ? int(int64_t(ntiles) * (k - nreg) / ntail) : 0;
+  const int t1 = on_tail ? int(int64_t(ntiles) * (k - nreg + 1) / ntail) : 0;
 
-  for (int q = xcd_logical_block(int(blockIdx.x), nwg); q < items; q += nwg) {
-    const int t = q % ntiles, sg = q / ntiles;
-    const int za = int(int64_t(nz) * sg / nseg);
-    const int zb = int(int64_t(nz) * (sg + 1) / nseg);
+  for (int it = 0;; ++it) {
+    int t, za, zb;
+    if (!on_tail) {
+      const int q = k + it * nreg;
+      if (q >= items) break;
+      t = q % ntiles;
+      const int sg = q / ntiles;
+      za = int(int64_t(zt) * sg / nseg);
+      zb = int(int64_t(zt) * (sg + 1) / nseg);
+    } else {
+      t = t0 + it;
+      if (t >= t1) break;
+      za = zt;
+      zb = nz;
+    }
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
     const int xw = wrapi(gx, nx), yw = wrapi(gy, ny);
@@ -354,19 +372,25 @@ int device_cus() {
 }
 
 template <int FMT, bool FORCE, bool MIXED = false>
-hipError_t launch_rows(int rows, dim3 grid, const StepParams& p, int ntx, int nty, int nseg, int nwg, hipStream_t s) {
-  switch (rows) {
+hipError_t launch_rows(const FluidPlan& c, const StepParams& p, hipStream_t s) {
+  const dim3 grid(uint32_t(c.nwg));
+  const int zt = p.g.nz - c.tail;
+  switch (c.rows) {
     case 8:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED>), grid, dim3(11 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED>), grid, dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+                         c.nwg, zt, c.ntail);
       break;
     case 10:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED>), grid, dim3(13 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED>), grid, dim3(13 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+                         c.nwg, zt, c.ntail);
       break;
     case 12:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED>), grid, dim3(15 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED>), grid, dim3(15 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+                         c.nwg, zt, c.ntail);
       break;
     default:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED>), grid, dim3(16 * RW), 0, s, p, ntx, nty, nseg, nwg);
+      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED>), grid, dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+                         c.nwg, zt, c.ntail);
       break;
   }
   return hipGetLastError();
@@ -375,7 +399,7 @@ hipError_t launch_rows(int rows, dim3 grid, const StepParams& p, int ntx, int nt
 
 const int kFluidTileRows[4] = {8, 10, 12, 13};
 
-FluidPlan fluid_plan(const Geometry& g, int rows, int cus) {
+FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail) {
   FluidPlan best{};
   double best_cost = 0.0;
   for (int r : kFluidTileRows) {
@@ -386,24 +410,43 @@ FluidPlan fluid_plan(const Geometry& g, int rows, int cus) {
     c.nty = (g.ny + r - 1) / r;
     const int64_t T = int64_t(c.ntx) * c.nty;
     // split z so that one wave of items fills the CUs when there are fewer
-    // tiles than CUs; then pick the split with the shortest critical path
+    // tiles than CUs; then pick the split with the shortest critical path,
+    // counted in plane steps (two extra planes start each item)
     double cost_best = 0.0;
-    int seg_best = 1;
+    int seg_best = 1, tail_best = 0, ntail_best = 0;
     const int smax = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(g.nz) / 4, 64)));
     for (int sgs = 1; sgs <= smax; ++sgs) {
       const int64_t items = T * sgs;
       const int64_t waves = (items + cus - 1) / cus;
-      const int64_t planes = (g.nz + sgs - 1) / sgs + 2;  // two extra planes start each segment
+      int64_t planes = (g.nz + sgs - 1) / sgs + 2;
+      int tail = 0, ntail = 0;
+      if (allow_tail && items < cus) {
+        // the idle CUs take the top s planes of every tile, kk tiles each
+        const int64_t E = std::min<int64_t>(cus - items, T);
+        const int64_t kk = (T + E - 1) / E;
+        for (int64_t sz = 1; sz <= int64_t(g.nz) - sgs; ++sz) {
+          const int64_t m = std::max<int64_t>((g.nz - sz + sgs - 1) / sgs + 2, kk * (sz + 2));
+          if (m < planes) {
+            planes = m;
+            tail = int(sz);
+            ntail = int(E);
+          }
+        }
+      }
       // time of one plane of one tile ~ the wavefronts of the workgroup
       const double cost = double(waves) * double(planes) * double(r + 3);
       if (sgs == 1 || cost < cost_best) {
         cost_best = cost;
         seg_best = sgs;
+        tail_best = tail;
+        ntail_best = ntail;
       }
     }
     c.nseg = seg_best;
+    c.tail = tail_best;
+    c.ntail = ntail_best;
     const int64_t items = T * seg_best;
-    c.nwg = int(std::min<int64_t>(items, cus));
+    c.nwg = int(std::min<int64_t>(items, cus)) + c.ntail;
     if (best.rows == 0 || cost_best < best_cost) {
       best = c;
       best_cost = cost_best;
@@ -415,21 +458,15 @@ FluidPlan fluid_plan(const Geometry& g, int rows, int cus) {
 hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s) {
   const FluidPlan c = fluid_plan(p.g, rows, device_cus());
   if (c.rows == 0) return hipErrorInvalidValue;
-  return launch_rows<FMT_Q16, false, true>(c.rows, dim3(uint32_t(c.nwg)), p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  return launch_rows<FMT_Q16, false, true>(c, p, s);
 }
 
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {
   const FluidPlan c = fluid_plan(p.g, rows, device_cus());
   if (c.rows == 0) return hipErrorInvalidValue;
-  const dim3 grid(uint32_t(c.nwg));
-  if (fmt == FMT_F32)
-    return p.force ? launch_rows<FMT_F32, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
-                   : launch_rows<FMT_F32, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
+  if (fmt == FMT_F32) return p.force ? launch_rows<FMT_F32, true>(c, p, s) : launch_rows<FMT_F32, false>(c, p, s);
   hipError_t e = hipErrorInvalidValue;
-  dispatch_codes(fmt, [&]<int F>() {
-    e = p.force ? launch_rows<F, true>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s)
-                : launch_rows<F, false>(c.rows, grid, p, c.ntx, c.nty, c.nseg, c.nwg, s);
-  });
+  dispatch_codes(fmt, [&]<int F>() { e = p.force ? launch_rows<F, true>(c, p, s) : launch_rows<F, false>(c, p, s); });
   return e;
 }
 

@@ -127,14 +127,19 @@ hipError_t launch_equilibrium_vjp(const float* rho, const float* u, const float*
 
 // Fused fluid pass over every cell (all axes treated periodic).  rows: tile
 // height (one of kFluidTileRows) or 0 to let fluid_plan choose.
+// The regular items (tile, z segment) cover z in [0, nz - tail) in nseg equal
+// segments; when they leave CUs idle, the top `tail` planes of every tile go
+// to ntail more workgroups, each taking a contiguous run of tiles.
 struct FluidPlan {
-  int rows;  // output rows per tile
+  int rows;   // output rows per tile
   int ntx, nty;
-  int nseg;  // z segments per tile
-  int nwg;   // workgroups launched
+  int nseg;   // z segments per tile below the tail
+  int nwg;    // workgroups launched (ntail of them on the tail)
+  int tail;   // planes in the tail (0: none)
+  int ntail;  // workgroups on the tail
 };
 extern const int kFluidTileRows[4];
-FluidPlan fluid_plan(const Geometry& g, int rows, int cus);
+FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail = true);
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s);
 
 // The paper's mixed-precision pipeline (Sec. 5.3, atomic accumulation), on

@@ -199,13 +199,14 @@ def debug_dither(idx, t, seed, mode):
 
 def fluid_plan(dims, tile_rows=0, cus=256):
     """The fluid pass's work split (host only): dict of tile rows, tiles along
-    x and y, z segments per tile and workgroups launched."""
+    x and y, z segments per tile, workgroups launched, planes in the tail and
+    the workgroups on it."""
     d = (ctypes.c_int * 3)(*[int(v) for v in dims])
-    out = (ctypes.c_int * 5)()
+    out = (ctypes.c_int * 7)()
     st = lib().lbm_fluid_plan(d, int(tile_rows), int(cus), out)
     if st != OK:
         raise LBMError(st, lib().lbm_last_error(None).decode())
-    return dict(zip(("rows", "ntx", "nty", "nseg", "nwg"), list(out)))
+    return dict(zip(("rows", "ntx", "nty", "nseg", "nwg", "tail", "ntail"), list(out)))
 
 
 class HomeLBM:

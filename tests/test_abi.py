@@ -3,6 +3,7 @@ exports every function include/homelbm.h declares; the header's option
 struct matches the binding's."""
 import ctypes
 
+import numpy as np
 import pytest
 import os
 import re
@@ -57,6 +58,56 @@ def test_no_oracle_in_product_path():
                 assert "homelbm_oracle" not in src, f
 
 
+def _xcd_logical_block(b, n):
+    x, k = b & 7, b >> 3
+    return x * (n >> 3) + min(x, n & 7) + k
+
+
+def _fluid_items(dims, p):
+    """The (tile, za, zb) items of every workgroup, enumerated as the fluid
+    kernel does from its launch arguments."""
+    nz = dims[2]
+    ntiles = p["ntx"] * p["nty"]
+    items = ntiles * p["nseg"]
+    nreg = p["nwg"] - p["ntail"]
+    zt = nz - p["tail"]
+    out = []
+    for b in range(p["nwg"]):
+        k = _xcd_logical_block(b, p["nwg"])
+        if k < nreg:
+            q = k
+            while q < items:
+                sg = q // ntiles
+                out.append((q % ntiles, zt * sg // p["nseg"], zt * (sg + 1) // p["nseg"]))
+                q += nreg
+        else:
+            j = k - nreg
+            for t in range(ntiles * j // p["ntail"], ntiles * (j + 1) // p["ntail"]):
+                out.append((t, zt, nz))
+    return out
+
+
+@pytest.mark.parametrize("cus", [256, 304, 80, 7])
+def test_fluid_items_cover_every_plane_once(cus):
+    """Every (tile, plane) of the grid belongs to exactly one work item, every
+    item is in range and non-empty, and the logical workgroup numbering is a
+    permutation."""
+    shapes = [(256, 256, 256), (1000, 400, 400), (37, 29, 23), (64, 17, 9), (5, 3, 2), (1, 1, 1),
+              (31, 45, 3), (2, 33, 4), (130, 53, 40), (128, 128, 128), (96, 24, 77), (64, 64, 1000)]
+    for dims in shapes:
+        for rows in (0, 8, 10, 12, 13):
+            p = homelbm.fluid_plan(dims, tile_rows=rows, cus=cus)
+            assert sorted(_xcd_logical_block(b, p["nwg"]) for b in range(p["nwg"])) == list(range(p["nwg"]))
+            assert p["ntail"] <= p["ntx"] * p["nty"] and p["tail"] < dims[2]
+            assert (p["tail"] == 0) == (p["ntail"] == 0)
+            ntiles = p["ntx"] * p["nty"]
+            seen = np.zeros((ntiles, dims[2]), dtype=np.int32)
+            for t, za, zb in _fluid_items(dims, p):
+                assert 0 <= t < ntiles and 0 <= za < zb <= dims[2], (dims, rows, p)
+                seen[t, za:zb] += 1
+            assert np.all(seen == 1), (dims, rows, p)
+
+
 def test_fluid_plan_host_logic():
     """The fluid pass's work split: every item maps to a tile and a z segment,
     one wave of items fills the CUs when tiles are fewer than CUs, and the
@@ -65,8 +116,13 @@ def test_fluid_plan_host_logic():
     p = plan((256, 256, 256))
     tiles = p["ntx"] * p["nty"]
     assert p["ntx"] == 4 and p["nty"] == -(-256 // p["rows"])
-    assert tiles * p["nseg"] <= 256 and p["nwg"] == tiles * p["nseg"]
+    assert tiles * p["nseg"] <= 256 and p["nwg"] == tiles * p["nseg"] + p["ntail"]
     assert tiles * (p["nseg"] + 1) > 256  # no further split fits in one wave
+    # the idle CUs share the top planes: both kinds of workgroup end together
+    assert p["ntail"] == 256 - tiles * p["nseg"] and 0 < p["tail"] < 256
+    per_tail = -(-tiles // p["ntail"])
+    reg = -(-(256 - p["tail"]) // p["nseg"]) + 2
+    assert max(reg, per_tail * (p["tail"] + 2)) < -(-256 // p["nseg"]) + 2
     q = plan((1000, 400, 400))
     assert q["ntx"] == 16 and q["nwg"] == 256
     for rows in (8, 10, 12, 13):
@@ -74,7 +130,7 @@ def test_fluid_plan_host_logic():
         assert r["rows"] == rows and r["ntx"] == 3 and r["nty"] == -(-53 // rows)
         assert 1 <= r["nwg"] <= 256 and r["nseg"] >= 1
     t = plan((1, 1, 1))
-    assert t["nwg"] == 1 and t["nseg"] == 1
+    assert t["nwg"] == 1 and t["nseg"] == 1 and t["tail"] == 0 and t["ntail"] == 0
     with pytest.raises(homelbm.LBMError):
         plan((8, 8, 8), tile_rows=7)
 
