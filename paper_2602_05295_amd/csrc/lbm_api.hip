@@ -199,6 +199,7 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   }
   p.g = geom(c);
   p.om1 = float(1.0 - 1.0 / c->tau);
+  if (c->fmt != FMT_F32) code_collision_consts(1.0 - 1.0 / c->tau, fmt_b2(c->fmt), p.nq_s, p.nq_d, p.nq_c);
   const int mode = c->fmt != FMT_F32 ? c->opt.dither_mode : 0;
   p.dither = mode != 0;
   p.key = dither_key(uint32_t(c->t), c->opt.seed, mode);

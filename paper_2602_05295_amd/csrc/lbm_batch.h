@@ -18,6 +18,7 @@ struct BatchDomain {
   int ty;
   int span;
   float om1;  // 1 - 1/tau of this domain
+  float nq_s, nq_d, nq_c;  // its code-space collision constants (16-bit codes)
 };
 
 // A run of planes [za, zb) of one strip: the unit of work of the fluid pass.

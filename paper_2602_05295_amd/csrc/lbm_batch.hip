@@ -154,11 +154,15 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
 
       float f0[8];
       if (active) {
-        const CellIn c = bdecode<FMT>(cur);
-        float Nn[6];
-        collide_neq(c.N, om1, Nn);
         float A[NA];
-        hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+        if constexpr (FMT == FMT_F32) {
+          const CellIn c = bdecode<FMT>(cur);
+          float Nn[6];
+          collide_neq(c.N, om1, Nn);
+          hermite_coeffs(c.dr, c.j, c.u, Nn, A);
+        } else {
+          post_collision_codes<FMT_Q16>(cur.v, D.nq_s, D.nq_d, D.nq_c, A);
+        }
         // ---- y pass: groups (n, l) with inputs m = 0, 1, 2 along y
         float fp[8], fm[8];
         recon3(A[A000], A[A010], A[A020], f0[0], fp[0], fm[0]);  // (0,0)
@@ -246,6 +250,9 @@ __device__ inline StepParams domain_params(const BatchStepParams& a, const Batch
   }
   p.g = Geometry{D.nx, D.ny, D.nz, 0};
   p.om1 = D.om1;
+  p.nq_s = D.nq_s;
+  p.nq_d = D.nq_d;
+  p.nq_c = D.nq_c;
   const int mode = FMT == FMT_Q16 ? a.dither_mode : 0;
   p.key = dither_key(*a.step + a.step_offset, a.seed, mode);
   p.dither = mode != 0;

@@ -108,7 +108,9 @@ std::string make_plan(const std::vector<int>& dims, const std::vector<double>& t
     if (!strip_shape(nx, ny, block, &rows, &ty, &span, &nstrips))
       return "domain " + std::to_string(d) + ": nx = " + std::to_string(nx) + " is too wide for " +
              std::to_string(block) + "-thread workgroups (at most " + std::to_string(block / 3) + ")";
-    out->doms[size_t(d)] = BatchDomain{offs[size_t(d)], nx, ny, nz, rows, ty, span, float(1.0 - 1.0 / taus[size_t(d)])};
+    BatchDomain& bd = out->doms[size_t(d)];
+    bd = BatchDomain{offs[size_t(d)], nx, ny, nz, rows, ty, span, float(1.0 - 1.0 / taus[size_t(d)]), 0.0f, 0.0f, 0.0f};
+    code_collision_consts(1.0 - 1.0 / taus[size_t(d)], 16, bd.nq_s, bd.nq_d, bd.nq_c);
     const double c = std::ceil(double(rows) * nx / 64.0);
     for (int s = 0; s < nstrips; ++s) {
       cols.push_back(Column{d, s, nz, c});

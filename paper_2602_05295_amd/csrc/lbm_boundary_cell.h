@@ -103,8 +103,18 @@ struct PostCell {
 
 template <int FMT>
 __device__ inline PostCell post_cell(const StepParams& a, uint32_t q) {
-  const CellIn c = load_cell_b<FMT>(a, q);
   PostCell s;
+  if constexpr (FMT != FMT_F32) {
+    if (!a.force) {  // the arithmetic of the fluid pass
+      uint32_t w[Codec<FMT>::W];
+#pragma unroll
+      for (int k = 0; k < Codec<FMT>::W; ++k)
+        w[k] = *reinterpret_cast<const uint32_t*>(static_cast<const char*>(a.in[k]) + q * 4u);
+      collide_codes<FMT>(w, a.nq_s, a.nq_d, a.nq_c, s.dr, s.rho, s.u, s.j, s.Nn);
+      return s;
+    }
+  }
+  const CellIn c = load_cell_b<FMT>(a, q);
   s.dr = c.dr;
   s.rho = c.rho;
   if (a.force) {
@@ -191,6 +201,10 @@ __device__ inline void rest_coeffs(const StepParams& a, float A[NA]) {
   } else {
     uint32_t w[Codec<FMT>::W];
     rest_codes<FMT>(w);
+    if (!a.force) {  // the arithmetic of the fluid pass
+      post_collision_codes<FMT>(w, a.nq_s, a.nq_d, a.nq_c, A);
+      return;
+    }
     c = Codec<FMT>::decode(w);
   }
   if (a.force)

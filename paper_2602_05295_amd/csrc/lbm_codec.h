@@ -16,7 +16,15 @@ struct Codec {
   static_assert(fmt_packed(FMT), "FMT_F32 has no codes");
   using PK = Packed<fmt_b1(FMT), fmt_b2(FMT)>;
   static constexpr int W = PK::W;
+  static constexpr float DR = PK::DR, DU = PK::DU;
   static __device__ inline CellIn decode(const uint32_t* w) { return cell_from_packed<PK>(w); }
+  // the ten codes as floats (exact), in the stored order
+  static __device__ inline void code_floats(const uint32_t* w, float q[10]) {
+    uint32_t k[10];
+    packed_codes<PK>(w, k);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) q[i] = float(k[i]);
+  }
   static __device__ inline void encode(float dr, const float j[3], const float P[6], uint32_t cell, uint32_t key,
                                        bool dith, uint32_t* w) {
     encode_packed<PK>(dr, j, P, cell, key, dith, w);
@@ -35,7 +43,15 @@ struct Codec {
 template <>
 struct Codec<FMT_Q16> {
   static constexpr int W = 5;
+  static constexpr float DR = Q_RHO_D, DU = Q_U_D;
   static __device__ inline CellIn decode(const uint32_t* w) { return cell_from_words(w); }
+  static __device__ inline void code_floats(const uint32_t* w, float q[10]) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      q[2 * i] = float(lo16(w[i]));
+      q[2 * i + 1] = float(hi16(w[i]));
+    }
+  }
   static __device__ inline void encode(float dr, const float j[3], const float P[6], uint32_t cell, uint32_t key,
                                        bool dith, uint32_t* w) {
     encode_cell(dr, j, P, cell, key, dith, w);
@@ -50,6 +66,40 @@ struct Codec<FMT_Q16> {
     return n;
   }
 };
+
+// App. A without force, applied to a cell's codes.  With N = lo + q dN the
+// post-collision stress (1 - 1/tau) dev(N) is om1 dN q + om1 lo off the
+// diagonal and om1 dN (q - (q_xx + q_yy + q_zz)/3) on it, where lo cancels:
+// N itself is never formed (nq_s = om1 dN, nq_d = nq_s / 3, nq_c = om1 lo).
+// Gives the moments of collide_neq applied to Codec<FMT>::decode(w).
+template <int FMT>
+__device__ inline void collide_codes(const uint32_t* w, float nq_s, float nq_d, float nq_c, float& dr, float& rho,
+                                     float u[3], float j[3], float Nn[6]) {
+  float q[10];
+  Codec<FMT>::code_floats(w, q);
+  dr = fmaf(q[0], Codec<FMT>::DR, Q_DRHO_LO);
+  rho = dr + 1.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = fmaf(q[1 + a], Codec<FMT>::DU, Q_U_LO);
+    j[a] = rho * u[a];
+  }
+  const float m = (q[4] + q[5] + q[6]) * nq_d;  // the sum of three codes is exact
+  Nn[0] = fmaf(q[4], nq_s, -m);
+  Nn[1] = fmaf(q[5], nq_s, -m);
+  Nn[2] = fmaf(q[6], nq_s, -m);
+  Nn[3] = fmaf(q[7], nq_s, nq_c);
+  Nn[4] = fmaf(q[8], nq_s, nq_c);
+  Nn[5] = fmaf(q[9], nq_s, nq_c);
+}
+
+// Post-collision coefficients of a cell's codes (App. A without force).
+template <int FMT>
+__device__ inline void post_collision_codes(const uint32_t* w, float nq_s, float nq_d, float nq_c, float A[NA]) {
+  float dr, rho, u[3], j[3], Nn[6];
+  collide_codes<FMT>(w, nq_s, nq_d, nq_c, dr, rho, u, j, Nn);
+  hermite_coeffs(dr, j, u, Nn, A);
+}
 
 // Codes of the rest state (rho = 1, u = 0, N = 0), rounded without dither.
 template <int FMT>

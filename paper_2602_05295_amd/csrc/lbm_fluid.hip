@@ -216,12 +216,15 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
       if (keep && p - 1 >= za && p - 1 < zb) lw_nxt = listed_pair(a.lc, row0 + plane * uint32_t(p - 1));
       if (p + 1 <= zb) nxt = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
 
-      const CellIn c = decode<FMT>(cur);
       float A[NA];
-      if constexpr (MIXED)
+      if constexpr (MIXED) {
+        const CellIn c = decode<FMT>(cur);
         hermite_coeffs(c.dr, c.j, c.u, c.N, A);  // the codes are post-collision already
-      else
-        post_collision<FORCE>(c, a.om1, a.hF, A);
+      } else if constexpr (FMT != FMT_F32 && !FORCE) {
+        post_collision_codes<FMT>(cur.v, a.nq_s, a.nq_d, a.nq_c, A);
+      } else {
+        post_collision<FORCE>(decode<FMT>(cur), a.om1, a.hF, A);
+      }
 
       // ---- y pass: groups (n, l) with inputs m = 0, 1, 2 along y
       float f0[8], fp[8], fm[8];

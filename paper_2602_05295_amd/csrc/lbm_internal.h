@@ -62,11 +62,26 @@ __device__ inline void side_load(const float* side, uint32_t slot, float m[10]) 
   m[9] = c.y;
 }
 
+// The constants of the code-space collision (post_collision_codes) for the
+// relaxation om1 = 1 - 1/tau and b2-bit stress codes: nq_s = om1 dN,
+// nq_d = nq_s / 3, nq_c = om1 lo_N, with the decode step dN and the range's
+// lower end lo_N = -0.1 (Sec. 5.3) as the kernels round them to float.
+inline void code_collision_consts(double om1, int b2, float& nq_s, float& nq_d, float& nq_c) {
+  const double dn = double(float(0.2 / double((1u << b2) - 1u)));
+  nq_s = float(om1 * dn);
+  nq_d = float(om1 * dn / 3.0);
+  nq_c = float(om1 * double(-0.1f));
+}
+
 struct StepParams {
   const void* in[10];  // state planes read (FP32: 10 float planes, Q16: 5 word planes)
   void* out[10];       // state planes written
   Geometry g;
   float om1;           // 1 - 1/tau
+  // App. A taken from the stress codes q of an integer format (no force):
+  // om1 dev(N) is nq_s q + nq_c off the diagonal and nq_s q - nq_d (q_xx +
+  // q_yy + q_zz) on it, with nq_s = om1 dN, nq_d = nq_s / 3, nq_c = om1 lo_N
+  float nq_s, nq_d, nq_c;
   uint32_t key;        // dither key of this step
   int dither;          // 0: round to nearest; else add the dither of `key`
   float u_in[3];
