@@ -99,6 +99,11 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_05295_amd.build` "
                            "(or __graft_entry__.build()); there is no fallback")
+    # One HIP runtime per process: torch ships its own libamdhip64 (soname
+    # libamdhip64.so.7) and asks for it by file name.  Loaded first, it
+    # satisfies this library's libamdhip64.so.7 too; loaded after this
+    # library, it would be a second runtime that finds no GPU.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     P = ctypes.POINTER

@@ -139,3 +139,17 @@ def test_default_options_have_no_force():
     o = homelbm.Options()
     assert homelbm.lib().lbm_default_options(ctypes.byref(o)) == 0
     assert list(o.force) == [0.0, 0.0, 0.0]
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not leave two HIP runtimes in the
+    process: the binding loads torch's first, and this library binds to it."""
+    import subprocess
+    import sys
+    code = ("from paper_2602_05295_amd import homelbm as H; H.lib(); "
+            "import re; maps = open('/proc/self/maps').read(); "
+            "paths = sorted(set(re.findall(r'\\S*libamdhip64\\S*', maps))); "
+            "assert len(paths) == 1, paths; print(paths[0])")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]

@@ -235,8 +235,32 @@ def _sample_cells(rng, N, mask=None, k=3000, extra=None):
     return cells
 
 
+def _plan_edge_cells(n):
+    """Cells of an n^3 grid on the fluid pass's work boundaries: the first and
+    last x and y of tiles, the first and last plane of every z segment and of
+    the z tail, as the plan for n^3 lays them out."""
+    import torch
+    from paper_2602_05295_amd import homelbm
+    plan = homelbm.fluid_plan((n, n, n), cus=torch.cuda.get_device_properties(0).multi_processor_count)
+    zt = n - plan["tail"]
+    zs = set()
+    for sg in range(plan["nseg"]):
+        za, zb = zt * sg // plan["nseg"], zt * (sg + 1) // plan["nseg"]
+        zs.update({za, zb - 1})
+    if plan["tail"]:
+        zs.update({zt, n - 1})
+    xs = sorted({v for t in range(plan["ntx"]) for v in (64 * t, min(64 * t + 63, n - 1))})
+    ys = sorted({v for t in range(plan["nty"]) for v in (plan["rows"] * t, min(plan["rows"] * (t + 1) - 1, n - 1))})
+    rng = np.random.default_rng(7)
+    z = np.array(sorted(zs))
+    pts = [(x, y, zz) for zz in z for x, y in zip(rng.choice(xs, 24), rng.choice(ys, 24))]
+    return np.array([x + n * (y + n * zz) for x, y, zz in pts])
+
+
 def test_fp32_256cubed_sampled(H, orc):
-    """The 256^3 decaying-turbulence configuration, one step, sampled cells."""
+    """The 256^3 decaying-turbulence configuration, one step, sampled cells
+    (random ones and cells on the work split's tile, segment and tail
+    boundaries)."""
     n = 256
     _note("fp32 256^3 sampled")
     u = W.random_solenoidal(n, n, n, 8.0, 0.1 / np.sqrt(3), seed=0).astype(np.float32)
@@ -248,11 +272,39 @@ def test_fp32_256cubed_sampled(H, orc):
         s.step(1)
         got = s.get_moments()
     rng = np.random.default_rng(0)
-    cells = _sample_cells(rng, n ** 3, extra=np.array([0, n - 1, n * n - 1, n ** 3 - 1]))
+    cells = _sample_cells(rng, n ** 3, extra=np.concatenate([np.array([0, n - 1, n * n - 1, n ** 3 - 1]),
+                                                             _plan_edge_cells(n)]))
     ref = orc.step_cells(_orc_params(orc, (n, n, n), 0.51), m0.astype(np.float64), cells)
     g = got.reshape(10, -1)[:, cells]
     err = group_rel_err(g, ref.T)
     assert max(err.values()) <= TOL32, err
+
+
+def test_q16_256cubed_sampled(H, orc):
+    """The headline configuration: 256^3 decaying turbulence in 16-bit
+    moments with dither per step, as the benchmark runs it (same launch
+    plan), one step; sampled codes within one code of the oracle's and at
+    most 1% off by one."""
+    n = 256
+    _note("q16 256^3 sampled")
+    u = W.random_solenoidal(n, n, n, 8.0, 0.1 / np.sqrt(3), seed=0).astype(np.float32)
+    rho = np.ones((n, n, n), np.float32)
+    with H.HomeLBM((n, n, n), 0.51, fmt="q16") as s:
+        s.set_options(dither_mode=1, seed=0)
+        s.set_equilibrium(rho, u)
+        s.step(3)
+        w0 = s.get_raw()
+        t0 = s.step_count
+        s.step(1)
+        got = s.get_raw()
+    rng = np.random.default_rng(2)
+    cells = _sample_cells(rng, n ** 3, extra=np.concatenate([np.array([0, n - 1, n * n - 1, n ** 3 - 1]),
+                                                             _plan_edge_cells(n)]))
+    ref = orc.q16_step_cells(_orc_params(orc, (n, n, n), 0.51), w0, cells, None, t=t0, seed=0, mode=1)
+    g = got.reshape(5, -1)[:, cells]
+    d = np.abs(unpack(g) - unpack(ref.T))
+    assert d.max() <= 1, d.max()
+    assert (d > 0).mean() < 0.01, (d > 0).mean()
 
 
 def test_q16_channel_sampled(H, orc):
