@@ -203,6 +203,7 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   const int mode = c->fmt != FMT_F32 ? c->opt.dither_mode : 0;
   p.dither = mode != 0;
   p.key = dither_key(uint32_t(c->t), c->opt.seed, mode);
+  p.stream_out = stream_out_state(state_bytes(c));
   for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
   for (int a = 0; a < 3; ++a) p.hF[a] = 0.5f * c->opt.force[a];
   p.force = (c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f) ? 1 : 0;

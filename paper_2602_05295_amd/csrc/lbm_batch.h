@@ -36,6 +36,7 @@ struct BatchStepParams {
   uint32_t step_offset;
   uint32_t seed;
   int dither_mode;            // 0 off, 1 per step, 2 static (Q16 only)
+  int stream_out;             // non-temporal stores of the new state (stream_out_state)
   int nwg;
   ListedCells lc;             // listed fluid cells by global cell index (lc.side == nullptr: none)
 };

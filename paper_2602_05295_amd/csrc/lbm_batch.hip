@@ -65,18 +65,29 @@ __device__ inline CellIn bdecode(const BRaw<FMT>& r) {
 }
 
 // cell: index within the domain (dither input); byte_off: address in the planes.
-template <int FMT>
+// STREAM: non-temporal stores, for a state larger than the caches, as in the
+// single-domain fluid pass.
+template <class T, bool STREAM>
+__device__ inline void bstore_word(void* plane, uint32_t byte_off, T v) {
+  T* q = reinterpret_cast<T*>(static_cast<char*>(plane) + byte_off);
+  if constexpr (STREAM)
+    __builtin_nontemporal_store(v, q);
+  else
+    *q = v;
+}
+
+template <int FMT, bool STREAM>
 __device__ inline void bstore(const BatchStepParams& a, uint32_t byte_off, uint32_t cell, uint32_t key, bool dith,
                               float dr, const float j[3], const float P[6]) {
   if constexpr (FMT == FMT_F32) {
     const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
 #pragma unroll
-    for (int k = 0; k < 10; ++k) *reinterpret_cast<float*>(static_cast<char*>(a.out[k]) + byte_off) = v[k];
+    for (int k = 0; k < 10; ++k) bstore_word<float, STREAM>(a.out[k], byte_off, v[k]);
   } else {
     uint32_t w[5];
     encode_cell(dr, j, P, cell, key, dith, w);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + byte_off) = w[k];
+    for (int k = 0; k < 5; ++k) bstore_word<uint32_t, STREAM>(a.out[k], byte_off, w[k]);
   }
 }
 
@@ -95,7 +106,7 @@ __device__ inline void bstate_arrived(const BRaw<FMT>& r) {
   for (int k = 0; k < K; ++k) asm volatile("" : : "v"(r.v[k]) : "memory");
 }
 
-template <int FMT, int NT>
+template <int FMT, int NT, bool STREAM = false>
 __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
   __shared__ float ly[16][NT];  // y movers (+, -) of 8 groups
   __shared__ float lx[18][NT];  // x movers (+, -) of 9 groups
@@ -139,7 +150,7 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
     auto store_plane = [&](int ps, const ListedPair& lws) {
       if (own) {
         const uint32_t cell = rowc + plane * uint32_t(ps);
-        bstore<FMT>(a, (D.off + cell) * 4u, cell, key, dith, sdr, sj, sP);
+        bstore<FMT, STREAM>(a, (D.off + cell) * 4u, cell, key, dith, sdr, sj, sP);
         const int slot = keep ? listed_slot_in(listed_word(lws, D.off + cell), D.off + cell) : -1;
         if (slot >= 0) side_store(a.lc.side, uint32_t(slot), sdr, sj, sP);  // a listed cell's unrounded moments
       }
@@ -286,18 +297,18 @@ __global__ void step_advance_kernel(uint32_t* step, uint32_t n) {
   if (threadIdx.x == 0) step[0] += n;
 }
 
-template <int FMT>
+template <int FMT, bool STREAM>
 hipError_t launch_nt(int block, const BatchStepParams& p, hipStream_t s) {
   const dim3 grid(uint32_t(p.nwg));
   switch (block) {
     case 256:
-      hipLaunchKernelGGL((strip_kernel<FMT, 256>), grid, dim3(256), 0, s, p);
+      hipLaunchKernelGGL((strip_kernel<FMT, 256, STREAM>), grid, dim3(256), 0, s, p);
       break;
     case 512:
-      hipLaunchKernelGGL((strip_kernel<FMT, 512>), grid, dim3(512), 0, s, p);
+      hipLaunchKernelGGL((strip_kernel<FMT, 512, STREAM>), grid, dim3(512), 0, s, p);
       break;
     case 1024:
-      hipLaunchKernelGGL((strip_kernel<FMT, 1024>), grid, dim3(1024), 0, s, p);
+      hipLaunchKernelGGL((strip_kernel<FMT, 1024, STREAM>), grid, dim3(1024), 0, s, p);
       break;
     default:
       return hipErrorInvalidValue;
@@ -318,7 +329,8 @@ int occupancy_of() {
 
 hipError_t launch_batch_fluid(int fmt, int block, const BatchStepParams& p, hipStream_t s) {
   if (p.nwg <= 0) return hipSuccess;
-  return fmt == FMT_F32 ? launch_nt<FMT_F32>(block, p, s) : launch_nt<FMT_Q16>(block, p, s);
+  if (fmt == FMT_F32) return p.stream_out ? launch_nt<FMT_F32, true>(block, p, s) : launch_nt<FMT_F32, false>(block, p, s);
+  return p.stream_out ? launch_nt<FMT_Q16, true>(block, p, s) : launch_nt<FMT_Q16, false>(block, p, s);
 }
 
 hipError_t launch_batch_boundary(int fmt, const BatchStepParams& p, const uint32_t* cells, const uint32_t* bits,

@@ -247,6 +247,7 @@ BatchStepParams params(const lbm_batch* b, int src, uint32_t k) {
   p.step_offset = k;
   p.seed = b->opt.seed;
   p.dither_mode = b->fmt == FMT_Q16 ? b->opt.dither_mode : 0;
+  p.stream_out = stream_out_state(plane_bytes(b) * size_t(nplanes(b)));
   p.nwg = b->nwg;
   if (b->n_fluid_b > 0) p.lc = ListedCells{b->d_lpack, b->d_side, uint32_t(b->n_fluid_b)};
   return p;

@@ -91,18 +91,30 @@ __device__ inline CellIn decode(const Raw<FMT>& r) {
 }
 
 // Writes the new moments of one cell: dr = rho - 1, j, P (xx yy zz xy xz yz).
-template <int FMT>
+// STREAM: non-temporal stores, for a state larger than the caches (see
+// stream_out_state); the written lines then leave L2 to the halo rows and
+// columns that neighbouring tiles read.
+template <class T, bool STREAM>
+__device__ inline void store_word(void* plane, uint32_t off, T v) {
+  T* p = reinterpret_cast<T*>(static_cast<char*>(plane) + off);
+  if constexpr (STREAM)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <int FMT, bool STREAM>
 __device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, const float j[3], const float P[6]) {
   const uint32_t off = cell * 4u;
   if constexpr (FMT == FMT_F32) {
     const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
 #pragma unroll
-    for (int k = 0; k < 10; ++k) *reinterpret_cast<float*>(static_cast<char*>(a.out[k]) + off) = v[k];
+    for (int k = 0; k < 10; ++k) store_word<float, STREAM>(a.out[k], off, v[k]);
   } else {
     uint32_t w[Codec<FMT>::W];
     Codec<FMT>::encode(dr, j, P, cell, a.key, a.dither != 0, w);
 #pragma unroll
-    for (int k = 0; k < Codec<FMT>::W; ++k) *reinterpret_cast<uint32_t*>(static_cast<char*>(a.out[k]) + off) = w[k];
+    for (int k = 0; k < Codec<FMT>::W; ++k) store_word<uint32_t, STREAM>(a.out[k], off, w[k]);
   }
 }
 
@@ -122,7 +134,7 @@ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v -
 // MIXED: the stream pass of the paper's mixed-precision pipeline (Sec. 5.3):
 // the codes hold post-collision moments, which are reconstructed without a
 // collision, and the new moments are stored as FP32 post-stream moments.
-template <int FMT, int TYR, bool FORCE, bool MIXED = false>
+template <int FMT, int TYR, bool FORCE, bool MIXED = false, bool STREAM = false>
 __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg, int zt, int ntail) {
   constexpr int OUT = MIXED ? int(FMT_F32) : FMT;
   constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
@@ -200,7 +212,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     auto store_plane = [&](int ps, const ListedPair& lw) {
       if (own) {
         const uint32_t cell = row + plane * uint32_t(ps);
-        store_cell<OUT>(a, cell, sdr, sj, sP);
+        store_cell<OUT, STREAM>(a, cell, sdr, sj, sP);
         if (keep && (lw.a.x | lw.a.y | lw.b.x | lw.b.y) != 0u) keep_listed(a.lc, cell, lw, sdr, sj, sP);
       }
     };
@@ -374,25 +386,25 @@ int device_cus() {
   return cached[dev];
 }
 
-template <int FMT, bool FORCE, bool MIXED = false>
+template <int FMT, bool FORCE, bool MIXED = false, bool STREAM = false>
 hipError_t launch_rows(const FluidPlan& c, const StepParams& p, hipStream_t s) {
   const dim3 grid(uint32_t(c.nwg));
   const int zt = p.g.nz - c.tail;
   switch (c.rows) {
     case 8:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED>), grid, dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED, STREAM>), grid, dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
     case 10:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED>), grid, dim3(13 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED, STREAM>), grid, dim3(13 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
     case 12:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED>), grid, dim3(15 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED, STREAM>), grid, dim3(15 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
     default:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED>), grid, dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED, STREAM>), grid, dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
   }
@@ -467,9 +479,16 @@ hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s) {
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {
   const FluidPlan c = fluid_plan(p.g, rows, device_cus());
   if (c.rows == 0) return hipErrorInvalidValue;
-  if (fmt == FMT_F32) return p.force ? launch_rows<FMT_F32, true>(c, p, s) : launch_rows<FMT_F32, false>(c, p, s);
+  // a body force takes the plain stores (force runs are the small ones)
+  if (fmt == FMT_F32)
+    return p.force ? launch_rows<FMT_F32, true>(c, p, s)
+                   : (p.stream_out ? launch_rows<FMT_F32, false, false, true>(c, p, s)
+                                   : launch_rows<FMT_F32, false>(c, p, s));
   hipError_t e = hipErrorInvalidValue;
-  dispatch_codes(fmt, [&]<int F>() { e = p.force ? launch_rows<F, true>(c, p, s) : launch_rows<F, false>(c, p, s); });
+  dispatch_codes(fmt, [&]<int F>() {
+    e = p.force ? launch_rows<F, true>(c, p, s)
+                : (p.stream_out ? launch_rows<F, false, false, true>(c, p, s) : launch_rows<F, false>(c, p, s));
+  });
   return e;
 }
 
