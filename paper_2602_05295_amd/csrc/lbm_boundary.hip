@@ -9,15 +9,20 @@
 namespace lbm {
 
 // Listed fluid cells: one lane each; entry e is slot e of the side buffer.
+// The pulled rest distributions, the same for every cell of the launch, are
+// evaluated once per workgroup into LDS.
 template <int FMT>
 __global__ void __launch_bounds__(256) boundary_fluid_kernel(StepParams a, const uint32_t* __restrict__ cells,
                                                              const uint32_t* __restrict__ bits,
                                                              const uint32_t* __restrict__ yz,
                                                              const uint32_t* __restrict__ order, int count) {
+  __shared__ float rest[27];
+  if (threadIdx.x < 27) rest_links<FMT>(a, int(threadIdx.x), rest);
+  __syncthreads();
   const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
   if (t >= count) return;
   const uint32_t e = order ? order[t] : uint32_t(t);
-  boundary_fix<FMT, false>(a, e, cells[e], bits[e], yz[e], nullptr);
+  boundary_fix<FMT, false, true>(a, e, cells[e], bits[e], yz[e], nullptr, rest);
 }
 
 // The same with the force and torque on each object summed (Sec. 3.2, last
@@ -29,12 +34,14 @@ __global__ void __launch_bounds__(256) boundary_fluid_forces_kernel(StepParams a
                                                                     const uint32_t* __restrict__ yz,
                                                                     const uint32_t* __restrict__ order, int count) {
   __shared__ float acc[256 * 6];
+  __shared__ float rest[27];
   for (int k = int(threadIdx.x); k < 256 * 6; k += 256) acc[k] = 0.0f;
+  if (threadIdx.x < 27) rest_links<FMT>(a, int(threadIdx.x), rest);
   __syncthreads();
   const int t = int(blockIdx.x) * 256 + int(threadIdx.x);
   if (t < count) {
     const uint32_t e = order ? order[t] : uint32_t(t);
-    boundary_fix<FMT, true>(a, e, cells[e], bits[e], yz[e], acc);
+    boundary_fix<FMT, true, true>(a, e, cells[e], bits[e], yz[e], acc, rest);
   }
   __syncthreads();
   for (int k = int(threadIdx.x); k < 256 * 6; k += 256)

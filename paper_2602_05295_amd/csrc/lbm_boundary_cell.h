@@ -232,9 +232,20 @@ __device__ inline void rest_coeffs(const StepParams& a, float A[NA]) {
 //   - TRACK: each solid link adds the momentum -(f_i(x) + f+_opp(i)(x)) c_i
 //     it delivers to its object, and the torque of that about the object's
 //     center, to acc (256 x 6, the workgroup's sums in LDS).
-template <int FMT, bool TRACK>
+// The distribution f+_i the fluid pass pulled from a listed solid neighbour,
+// for every direction i (eval_link of rest_coeffs), into rest[27].
+template <int FMT>
+__device__ inline void rest_links(const StepParams& a, int i, float* rest) {
+  float Arest[NA];
+  rest_coeffs<FMT>(a, Arest);
+  rest[i] = eval_link(Arest, i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1);
+}
+
+// TABLE: rest holds the 27 values of rest_links (one launch's constants, in
+// LDS); else they are evaluated here (the batch, whose cells differ in tau).
+template <int FMT, bool TRACK, bool TABLE = false>
 __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t cell, uint32_t b, uint32_t yz,
-                                    float* acc) {
+                                    float* acc, const float* rest = nullptr) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int y = int(yz & 0xFFFFu), z = int(yz >> 16);
   float m[10];
@@ -244,8 +255,8 @@ __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t ce
   hermite_coeffs(own.dr, own.j, own.u, own.Nn, Aown);
   uint32_t bb = b & 0x7FFFFFFu & ~(1u << 13);
   if (bb) {
-    float Arest[NA];
-    rest_coeffs<FMT>(a, Arest);
+    float Arest[TABLE ? 1 : NA];
+    if constexpr (!TABLE) rest_coeffs<FMT>(a, Arest);
     const int x = int(cell - uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z)));
     while (bb) {
       const int i = __ffs(bb) - 1;
@@ -267,7 +278,12 @@ __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t ce
           fnew = eval_link(Ap, cx, cy, cz);
         }
       }
-      add_link(m, cx, cy, cz, fnew - eval_link(Arest, cx, cy, cz));
+      float pulled;
+      if constexpr (TABLE)
+        pulled = rest[i];
+      else
+        pulled = eval_link(Arest, cx, cy, cz);
+      add_link(m, cx, cy, cz, fnew - pulled);
       if constexpr (TRACK) {
         float px[3], py[3], pz[3];
         basis1(cx, px);
