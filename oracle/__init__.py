@@ -121,6 +121,7 @@ def lib():
         L.orc_q16_step_cells.argtypes = [_P(Params), _u8, _u32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.c_int64, _i64, _u32, ctypes.c_int]
         L.orc_adjoint_step.argtypes = [_P(Params), _u8, _dp, _dp, _dp, ctypes.c_int]
+        L.orc_adjoint_step_cells.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int64, _i64, _dp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -297,6 +298,20 @@ def adjoint_step(params: Params, m_t, lam_next, mask=None):
     out = np.zeros_like(m_t)
     mk, mp = _mask_ptr(mask)
     if lib().orc_adjoint_step(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), _ptr(out, _dp), 1) != 0:
+        raise ValueError("the oracle's adjoint follows bounce-back walls only (wall_rule 0)")
+    return out
+
+
+def adjoint_step_cells(params: Params, m_t, lam_next, cells, mask=None):
+    """lam_prev = J(m_t)^T lam_next at the given cells only, (ncells, 10):
+    the same transpose as adjoint_step, gathered per source cell."""
+    m_t = _check_field(m_t, params)
+    lam_next = _check_field(lam_next, params)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((cells.size, 10))
+    mk, mp = _mask_ptr(mask)
+    if lib().orc_adjoint_step_cells(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), cells.size,
+                                    _ptr(cells, _i64), _ptr(out, _dp), 1) != 0:
         raise ValueError("the oracle's adjoint follows bounce-back walls only (wall_rule 0)")
     return out
 

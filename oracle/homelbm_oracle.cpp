@@ -919,4 +919,91 @@ int orc_adjoint_step(const OrcParams* P, const uint8_t* mask, const double* m_t,
   return 0;
 }
 
+// lam_prev at chosen cells only: the same transpose as orc_adjoint_step,
+// gathered per source cell s instead of scattered per output cell.  f+_i(s)
+// reaches the new moments of (a) c = s + c_i by pull streaming (c fluid, x
+// inside the domain when the x faces are open), (b) with open faces and s on
+// the outflow face x = nx - 1, the face cell (nx - 1, y + c_iy, z + c_iz) for
+// c_ix = -1 (zero gradient), (c) s itself on a bounce-back link: f_opp(i)(s)
+// = f+_i(s) when s + c_i is solid; and (d) on the inflow face x = 0 the
+// inflow distributions of s depend on the post-collision moments of s.
+// Solid cells get zeros.  out: ncells x 10.
+int orc_adjoint_step_cells(const OrcParams* P, const uint8_t* mask, const double* m_t, const double* lam_next,
+                           int64_t ncells, const int64_t* cells, double* out, int nthreads) {
+  (void)nthreads;
+  if (P->wall_rule != 0) return -1;
+  Grid<double> G(*P, mask);
+  const int64_t N = G.N;
+  const bool lit = P->literal_xyz != 0;
+  auto phi_of = [](int i, double phi[10]) {
+    const double* cv = LAT.cd[i];
+    phi[0] = 1.0;
+    for (int a = 0; a < 3; ++a) phi[1 + a] = cv[a];
+    for (int p = 0; p < 6; ++p) phi[4 + p] = cv[PA[p]] * cv[PB[p]] - CS2 * kd(PA[p], PB[p]);
+  };
+  auto lam_dot = [&](int i, int64_t c) {
+    double phi[10];
+    phi_of(i, phi);
+    double lf = 0.0;
+    for (int k = 0; k < 10; ++k) lf += phi[k] * lam_next[k * N + c];
+    return lf;
+  };
+  for (int64_t n = 0; n < ncells; ++n) {
+    const int64_t s = cells[n];
+    double* o = out + 10 * n;
+    for (int k = 0; k < 10; ++k) o[k] = 0.0;
+    if (G.solid(s)) continue;
+    const int x = int(s % P->nx), y = int((s / P->nx) % P->ny), z = int(s / (int64_t(P->nx) * P->ny));
+    // J[i][k] = d f+_i(s) / d m_k(s)
+    double J[27][10];
+    for (int k = 0; k < 10; ++k) {
+      cd m[10];
+      for (int q = 0; q < 10; ++q) m[q] = cd(m_t[q * N + s], q == k ? CS_H : 0.0);
+      const Cell<cd> post = collide(to_cell(m), P->F, P->tau);
+      for (int i = 0; i < 27; ++i) J[i][k] = hermite_f(i, post, lit).imag() / CS_H;
+    }
+    for (int i = 0; i < 27; ++i) {
+      const int cx = LAT.c[i][0], cy = LAT.c[i][1], cz = LAT.c[i][2];
+      double lf = 0.0;
+      // (a) pull streaming into c = s + c_i
+      int tx = x + cx;
+      bool inside = true;
+      if (P->inflow) inside = tx >= 0 && tx < P->nx;
+      else tx = wrap(tx, P->nx);
+      if (inside) {
+        const int64_t c = G.idx(tx, wrap(y + cy, P->ny), wrap(z + cz, P->nz));
+        if (!G.solid(c)) lf += lam_dot(i, c);
+        // (c) bounce-back: s + c_i solid sends f+_i(s) back into s as f_opp(i)(s)
+        else lf += lam_dot(LAT.opp[i], s);
+      }
+      // (b) zero-gradient outflow: face cells take f+_i of their face neighbour
+      if (P->inflow && x == P->nx - 1 && cx == -1) {
+        const int64_t c = G.idx(P->nx - 1, wrap(y + cy, P->ny), wrap(z + cz, P->nz));
+        if (!G.solid(c)) lf += lam_dot(i, c);
+      }
+      if (lf != 0.0)
+        for (int k = 0; k < 10; ++k) o[k] += lf * J[i][k];
+    }
+    // (d) the inflow distributions of s (c_ix = +1 on x = 0)
+    if (P->inflow && x == 0) {
+      for (int i = 0; i < 27; ++i) {
+        if (LAT.c[i][0] != +1) continue;
+        const double lf = lam_dot(i, s);
+        for (int k = 0; k < 10; ++k) {
+          cd m[10];
+          for (int q = 0; q < 10; ++q) m[q] = cd(m_t[q * N + s], q == k ? CS_H : 0.0);
+          const Cell<cd> qq = collide(to_cell(m), P->F, P->tau);
+          Cell<cd> pp;
+          pp.rho = qq.rho;
+          for (int a = 0; a < 3; ++a) pp.u[a] = cd(P->u_in[a], 0.0);
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) pp.S[a][b] = cd(P->u_in[a] * P->u_in[b]) + (qq.S[a][b] - qq.u[a] * qq.u[b]);
+          o[k] += lf * hermite_f(i, pp, lit).imag() / CS_H;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
 }  // extern "C"

@@ -129,3 +129,44 @@ def test_rollout_gradient_matches_oracle(orc, torch_mod):
     assert abs(loss_gpu - loss_orc) / loss_orc < 1e-4
     rel = np.linalg.norm(g_gpu - g_orc) / np.linalg.norm(g_orc)
     assert rel < 1e-4, rel
+
+
+def test_adjoint_step_full_size_sampled(orc, torch_mod):
+    """The adjoint benchmark's configuration: 128^3 with ~5% sphere obstacles,
+    FP32, tau = 0.6, at the state reached after 10 steps from its initial
+    field.  One adjoint step, lam_prev at 3000+ sampled cells (among them
+    fluid cells next to a wall) against the oracle's transpose gathered at
+    those cells, within 2e-5 per moment group."""
+    torch = torch_mod
+    from paper_2602_05295_amd.homelbm import HomeLBM
+    n = 128
+    dims = (n, n, n)
+    _note("adjoint step full size sampled", dims)
+    mask = W.sphere_mask(n, n, n, phi=0.05, rmin=4.0, rmax=12.0, seed=0)
+    u0 = W.random_solenoidal(n, n, n, 4.0, 0.05, seed=0).astype(np.float32)
+    rng = np.random.default_rng(8)
+    lam = rng.standard_normal((10, n, n, n)).astype(np.float32)
+    with HomeLBM(dims, 0.6, mask=mask) as s:
+        s.set_equilibrium(np.ones((n, n, n), np.float32), u0)
+        s.step(10)
+        m = s.get_moments()
+        raw = _raw_from_moments(m)
+        mt = torch.from_numpy(raw).cuda()
+        ln = torch.from_numpy(lam).cuda()
+        lp = torch.empty_like(ln)
+        s.adjoint_step(mt, ln, lp)
+        s.synchronize()
+        got = lp.cpu().numpy().reshape(10, -1)
+    fluid = np.flatnonzero(mask.ravel() == 0)
+    solid = np.flatnonzero(mask.ravel() != 0)
+    near = (rng.choice(solid, 1500) + rng.choice([-1, 1, -n, n, -n * n, n * n], 1500)) % (n ** 3)
+    near = near[mask.ravel()[near] == 0]
+    cells = np.unique(np.concatenate([rng.choice(fluid, 2000, replace=False), near]))
+    m64 = raw.astype(np.float64)
+    m64[0] += 1.0
+    P = orc.make_params(dims, 0.6)
+    ref = orc.adjoint_step_cells(P, m64, lam.astype(np.float64), cells, mask).T
+    g = got[:, cells]
+    for grp in (slice(0, 1), slice(1, 4), slice(4, 10)):
+        err = np.abs(g[grp] - ref[grp]).max() / np.abs(ref[grp]).max()
+        assert err < 2e-5, (grp, err)

@@ -56,3 +56,27 @@ def test_adjoint_finite_differences(orc, inflow):
         fd = (loss(m0 + h * v) - loss(m0 - h * v)) / (2 * h)
         ad = (lam * v).sum()
         assert abs(fd - ad) <= 1e-7 * abs(ad), (d, fd, ad)
+
+
+@pytest.mark.parametrize("case", ["periodic", "walls", "faces"])
+def test_gathered_adjoint_equals_scattered(orc, case):
+    """adjoint_step_cells (gathered per source cell, used at sampled cells of
+    large grids) equals adjoint_step (scattered per output cell) at every
+    cell: periodic, with walls, and with open faces and walls."""
+    dims = (9, 7, 6)
+    mask = None
+    inflow = case == "faces"
+    if case != "periodic":
+        mask = W.sphere_mask(*dims, phi=0.12, rmin=1.0, rmax=1.8, seed=2)
+        if inflow:
+            mask[:, :, :3] = 0
+            mask[:, :, -3:] = 0
+            mask[:, 2:5, 3:6] = 1
+        assert mask.any()
+    m = W.random_moments(*dims, seed=11, dj=0.02, dp=0.003)
+    lam = np.random.default_rng(12).standard_normal(m.shape)
+    P = orc.make_params(dims, 0.6, inflow=inflow, u_in=(0.05, 0.01, -0.02))
+    ref = orc.adjoint_step(P, m, lam, mask)
+    cells = np.arange(np.prod(dims))
+    got = orc.adjoint_step_cells(P, m, lam, cells, mask)
+    assert np.abs(got.T - ref.reshape(10, -1)).max() < 1e-13 * np.abs(ref).max()
