@@ -228,6 +228,10 @@ def channel(steps=20):
             "mlups": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
             "fluid_kernel_ms": round(prof["fluid_ms"] / prof["fluid_launches"], 4),
             "boundary_kernel_ms": round(prof["boundary_ms"] / max(prof["boundary_launches"], 1), 4),
+            # the fluid pass's algorithmic bytes (one 16-bit state read and written, 40 B per cell)
+            "fluid_GBs": round(cells * 40 / (prof["fluid_ms"] / prof["fluid_launches"] * 1e-3) / 1e9, 1),
+            "fluid_hbm_frac": round(cells * 40 / (prof["fluid_ms"] / prof["fluid_launches"] * 1e-3) / 1e9
+                                    / HBM_PEAK_GBS, 4),
             "unhealthy_values": int(bad),
             "paper_mixed_pipeline": mixed}
 
