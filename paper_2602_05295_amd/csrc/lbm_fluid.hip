@@ -33,6 +33,9 @@
 #include "lbm_codec.h"
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 
 namespace lbm {
 
@@ -414,7 +417,8 @@ hipError_t launch_rows(const FluidPlan& c, const StepParams& p, hipStream_t s) {
 
 const int kFluidTileRows[4] = {8, 10, 12, 13};
 
-FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail) {
+namespace {
+FluidPlan plan_uncached(const Geometry& g, int rows, int cus, bool allow_tail) {
   FluidPlan best{};
   double best_cost = 0.0;
   for (int r : kFluidTileRows) {
@@ -433,7 +437,7 @@ FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail) {
     for (int sgs = 1; sgs <= smax; ++sgs) {
       const int64_t items = T * sgs;
       const int64_t waves = (items + cus - 1) / cus;
-      int64_t planes = (g.nz + sgs - 1) / sgs + 2;
+      int64_t path = waves * ((g.nz + sgs - 1) / sgs + 2);
       int tail = 0, ntail = 0;
       if (allow_tail && items < cus) {
         // the idle CUs take the top s planes of every tile, kk tiles each
@@ -441,15 +445,35 @@ FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail) {
         const int64_t kk = (T + E - 1) / E;
         for (int64_t sz = 1; sz <= int64_t(g.nz) - sgs; ++sz) {
           const int64_t m = std::max<int64_t>((g.nz - sz + sgs - 1) / sgs + 2, kk * (sz + 2));
-          if (m < planes) {
-            planes = m;
+          if (m < path) {
+            path = m;
             tail = int(sz);
             ntail = int(E);
           }
         }
+      } else if (allow_tail && items % cus != 0) {
+        // more than one wave, the last one partial: E workgroups take the top
+        // s planes of every tile, kk tiles each, and the other cus - E run
+        // the regular items in rounds
+        const int64_t emax = std::min<int64_t>(T, cus / 4);
+        for (int64_t E = 1; E <= emax; ++E) {
+          const int64_t rounds = (items + (cus - E) - 1) / (cus - E);
+          const int64_t kk = (T + E - 1) / E;
+          // s where rounds ((nz - s)/sgs + 2) = kk (s + 2), then its neighbours
+          const double s0 = (double(rounds) * g.nz / sgs + 2.0 * rounds - 2.0 * kk) / (double(kk) + double(rounds) / sgs);
+          for (int64_t sz = std::max<int64_t>(1, int64_t(s0) - 2); sz <= std::min<int64_t>(g.nz - sgs, int64_t(s0) + 3);
+               ++sz) {
+            const int64_t m = std::max<int64_t>(rounds * ((g.nz - sz + sgs - 1) / sgs + 2), kk * (sz + 2));
+            if (m < path) {
+              path = m;
+              tail = int(sz);
+              ntail = int(E);
+            }
+          }
+        }
       }
       // time of one plane of one tile ~ the wavefronts of the workgroup
-      const double cost = double(waves) * double(planes) * double(r + 3);
+      const double cost = double(path) * double(r + 3);
       if (sgs == 1 || cost < cost_best) {
         cost_best = cost;
         seg_best = sgs;
@@ -461,13 +485,28 @@ FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail) {
     c.tail = tail_best;
     c.ntail = ntail_best;
     const int64_t items = T * seg_best;
-    c.nwg = int(std::min<int64_t>(items, cus)) + c.ntail;
+    c.nwg = c.ntail == 0 ? int(std::min<int64_t>(items, cus))
+                         : (items < cus ? int(items) + c.ntail : cus);
     if (best.rows == 0 || cost_best < best_cost) {
       best = c;
       best_cost = cost_best;
     }
   }
   return best;
+}
+}  // namespace
+
+FluidPlan fluid_plan(const Geometry& g, int rows, int cus, bool allow_tail) {
+  // plans are looked up per launch; the search runs once per shape
+  static std::mutex mu;
+  static std::map<std::array<int, 6>, FluidPlan> cache;
+  const std::array<int, 6> key{g.nx, g.ny, g.nz, rows, cus, allow_tail ? 1 : 0};
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const FluidPlan c = plan_uncached(g, rows, cus, allow_tail);
+  if (cache.size() < 4096) cache.emplace(key, c);
+  return c;
 }
 
 hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s) {
