@@ -338,7 +338,20 @@ def cpu_baseline(u, steps=8):
     dt = time.perf_counter() - t0
     cells = N ** 3
     return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps of the full {N}^3 field, {dt:.1f} s on {threads} host threads"}
+            "sample": f"{steps} FP64 oracle steps of the full {N}^3 field, {dt:.1f} s on {threads} host threads",
+            "cpu": host_cpu()}
+
+
+def host_cpu() -> str:
+    """The host's CPU model, as /proc/cpuinfo names it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
