@@ -72,7 +72,7 @@ enum lbm_status {
   LBM_ERR_INVALID_ARG = 1,   /* bad dimensions, tau, mask, pointer or size */
   LBM_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
   LBM_ERR_DEVICE = 3,        /* a HIP call failed (message names it) */
-  LBM_ERR_UNSUPPORTED = 4,   /* valid request this build does not implement */
+  LBM_ERR_UNSUPPORTED = 4,   /* valid request the library does not implement */
   LBM_ERR_UNSTABLE = 5       /* the state holds non-finite values or saturated codes */
 };
 
