@@ -137,15 +137,18 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
     const float om1 = D.om1;
     const int za = sg.za, zb = sg.zb;
 
-    float wp2[6], wp1[6], w0[6];
+    // z window: fp of planes p - 2 / p - 1 and f0 of plane p - 1, in paired
+    // buffers whose roles swap between the two planes of a trip (no register
+    // copies from one plane to the next), as in the single-domain fluid pass
+    float wA[6], wB[6], zA[6], zB[6];
 #pragma unroll
-    for (int g = 0; g < 6; ++g) wp2[g] = wp1[g] = w0[g] = 0.0f;
+    for (int g = 0; g < 6; ++g) wA[g] = wB[g] = zA[g] = zB[g] = 0.0f;
 
-    BRaw<FMT> nxt1{};
-    if (active) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(za - 1, nz))) * 4u);
+    BRaw<FMT> bufA{}, bufB{};
+    if (active) bufA = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(za - 1, nz))) * 4u);
     const bool keep = own && a.lc.side != nullptr;  // listed cells to look for
-    ListedPair lw{};                                // packed bitmap words of the cells stored next
-    // new moments of the plane finished by the previous iteration
+    ListedPair lwA{}, lwB{};                        // packed bitmap words of the cells stored next
+    // new moments of the plane finished by the previous step
     float sdr = 0.0f, sj[3] = {0.0f, 0.0f, 0.0f}, sP[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     auto store_plane = [&](int ps, const ListedPair& lws) {
       if (own) {
@@ -155,13 +158,16 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
         if (slot >= 0) side_store(a.lc.side, uint32_t(slot), sdr, sj, sP);  // a listed cell's unrounded moments
       }
     };
-    for (int p = za - 1; p <= zb; ++p) {
-      const BRaw<FMT> cur = nxt1;
+    // One plane p: cur holds its state, nxt receives plane p + 1's; wp2 holds
+    // the fp of plane p - 2 and receives this plane's; w0 holds the f0 of plane
+    // p - 1, w0out receives this plane's; lw_cur belongs to the cell of plane
+    // p - 2 (stored now), lw_nxt receives that of plane p - 1.
+    auto plane_step = [&](int p, const BRaw<FMT>& cur, BRaw<FMT>& nxt, float (&wp2)[6], const float (&w0)[6],
+                          float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt) {
       bstate_arrived<FMT>(cur);
-      const ListedPair lw_cur = lw;  // words of plane p - 2
       if (p - 2 >= za) store_plane(p - 2, lw_cur);
-      if (keep && p - 1 >= za && p - 1 < zb) lw = listed_pair(a.lc, D.off + rowc + plane * uint32_t(p - 1));
-      if (active && p + 1 <= zb) nxt1 = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(p + 1, nz))) * 4u);
+      if (keep && p - 1 >= za && p - 1 < zb) lw_nxt = listed_pair(a.lc, D.off + rowc + plane * uint32_t(p - 1));
+      if (active && p + 1 <= zb) nxt = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(p + 1, nz))) * 4u);
 
       float f0[8];
       if (active) {
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
         recon3(X20[0], X20[1], X20[2], zf0[3], zfp[3], zfm[3]);
         recon3(X11[0], X11[1], X11[2], zf0[4], zfp[4], zfm[4]);
         recon3(X02[0], X02[1], X02[2], zf0[5], zfp[5], zfm[5]);
-        if (p > za) {  // plane p - 1 is complete; stored in the next iteration
+        if (p > za) {  // plane p - 1 is complete; stored in the next step
           proj3(w0[0], wp2[0], zfm[0], sdr, sj[2], sP[2]);  // (0,0,c): rho-1, jz, Pzz
           proj2(w0[1], wp2[1], zfm[1], sj[0], sP[4]);       // (1,0,c): jx, Pxz
           proj2(w0[2], wp2[2], zfm[2], sj[1], sP[5]);       // (0,1,c): jy, Pyz
@@ -239,13 +245,25 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
         }
 #pragma unroll
         for (int g = 0; g < 6; ++g) {
-          wp2[g] = wp1[g];
-          wp1[g] = zfp[g];
-          w0[g] = zf0[g];
+          wp2[g] = zfp[g];  // fp(p - 2) is used up: this slot now holds fp(p)
+          w0out[g] = zf0[g];
         }
       }
+    };
+
+    // at the start of a trip: state in bufA, fp(p - 2) in wA, fp(p - 1) in wB, f0(p - 1) in zA
+    for (int p = za - 1; p <= zb; p += 2) {
+      plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
+      if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA);
     }
-    if (zb - 1 >= za) store_plane(zb - 1, lw);
+    // the last step (plane zb) loaded the words of plane zb - 1 into lwB when
+    // it ran first in its trip, else into lwA
+    if (zb - 1 >= za) {
+      if (((zb - za) & 1) != 0)
+        store_plane(zb - 1, lwB);
+      else
+        store_plane(zb - 1, lwA);
+    }
   }
 }
 
