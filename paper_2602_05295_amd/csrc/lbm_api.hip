@@ -36,6 +36,7 @@ struct lbm_ctx {
   uint32_t* d_order = nullptr;            // boundary pass order of the fluid entries: face cells first
   float* d_side = nullptr;
   int64_t n_fluid_b = 0, n_solid_b = 0;
+  int64_t n_fluid_run = 0;                // fluid entries the boundary pass visits (d_order's length, if any)
   uint32_t* d_counters = nullptr;     // 3 list counters
   unsigned long long* d_bad = nullptr;
   uint8_t* d_flags = nullptr;         // adjoint cell flags (built on first use)
@@ -96,7 +97,7 @@ void free_list(lbm_ctx* c) {
   c->d_lpack = nullptr;
   c->d_order = nullptr;
   c->d_side = nullptr;
-  c->n_fluid_b = c->n_solid_b = 0;
+  c->n_fluid_b = c->n_solid_b = c->n_fluid_run = 0;
   c->list_built = false;
   c->flags_valid = false;
 }
@@ -142,6 +143,7 @@ int build_list(lbm_ctx* c) {
   if (e == hipSuccess) e = hipMemcpy(c->d_lpack, hpack.data(), (nchunks + 1) * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(c, e, "uploading list offsets");
   const int64_t total = int64_t(cnt[0]) + cnt[1];
+  int64_t run_fluid = cnt[0];
   if (total > 0) {
     e = hipMalloc(&c->d_cells, size_t(total) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->d_bits, size_t(total) * 4);
@@ -156,21 +158,29 @@ int build_list(lbm_ctx* c) {
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "classify (fill)");
     if (g.inflow && cnt[0] > 0) {
-      // face cells (nine changed links each, with loads) in wavefronts of their own
+      // The boundary pass visits the inflow face first (nine links each, in
+      // wavefronts of their own), then the other cells with changed links.
+      // An outflow face cell with no other flag is skipped: the fluid pass
+      // already wrote its final state.  (The list keeps it for the mixed
+      // pipeline and the adjoint.)
       std::vector<uint32_t> hbits(cnt[0]), order;
       order.reserve(cnt[0]);
       e = hipMemcpy(hbits.data(), c->d_bits, size_t(cnt[0]) * 4, hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_fail(c, e, "reading list flags");
       for (uint32_t k = 0; k < cnt[0]; ++k)
-        if (hbits[k] & (BIT_INFLOW | BIT_OUTFLOW)) order.push_back(k);
+        if (hbits[k] & BIT_INFLOW) order.push_back(k);
       for (uint32_t k = 0; k < cnt[0]; ++k)
-        if (!(hbits[k] & (BIT_INFLOW | BIT_OUTFLOW))) order.push_back(k);
-      e = hipMalloc(&c->d_order, size_t(cnt[0]) * 4);
-      if (e == hipSuccess) e = hipMemcpy(c->d_order, order.data(), size_t(cnt[0]) * 4, hipMemcpyHostToDevice);
-      if (e != hipSuccess) return hip_fail(c, e, "uploading the boundary order");
+        if (!(hbits[k] & BIT_INFLOW) && (hbits[k] & ~BIT_OUTFLOW) != 0u) order.push_back(k);
+      if (!order.empty()) {
+        e = hipMalloc(&c->d_order, order.size() * 4);
+        if (e == hipSuccess) e = hipMemcpy(c->d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "uploading the boundary order");
+      }
+      run_fluid = int64_t(order.size());
     }
   }
   c->n_fluid_b = cnt[0];
+  c->n_fluid_run = run_fluid;
   c->n_solid_b = cnt[1];
   c->list_built = true;
   c->list_inflow = g.inflow;
@@ -227,8 +237,11 @@ int enqueue_pass(lbm_ctx* c, const void* in, void* out, hipEvent_t ev[4]) {
   if (n > 0) {
     if (ev) e = hipEventRecord(ev[2], c->stream);
     if (e == hipSuccess)
-      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_b),
-                          int(c->n_solid_b), c->stream);
+      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_run), 0,
+                          c->stream);
+    if (e == hipSuccess && c->n_solid_b > 0)
+      e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b),
+                          c->stream);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }

@@ -221,12 +221,12 @@ __device__ inline void rest_coeffs(const StepParams& a, float A[NA]) {
 //   - bounce-back link i (source solid): new f+_opp(i)(x); pulled: f+_i of
 //     the stored rest state (rest_coeffs), no load;
 //   - inflow link (cx = 1 on the inflow face): new f+_i with the inflow
-//     coefficients of x, pulled f+_i of the periodic image (nx-1, y-cy, z-cz);
-//   - outflow link (cx = -1 on the outflow face): new f+_i of (nx-1, y-cy,
-//     z-cz), pulled f+_i of the periodic image (0, y-cy, z-cz).
-// Bounce-back links are walked per lane (a bit scan); face links, the same
-// nine for every face cell, in lockstep so that neighbouring face cells'
-// loads coalesce.
+//     coefficients of x; the fluid pass pulled nothing there (zero), so no
+//     source is read;
+//   - outflow link (cx = -1 on the outflow face): the fluid pass pulled it
+//     from a copy of the plane x = nx - 1, which is the zero-gradient value,
+//     so nothing changes (a cell with no other flag is not visited at all).
+// Bounce-back links are walked per lane (a bit scan).
 //   - with wall rule 1 a solid link's new f+ is instead reconstructed at the
 //     link midpoint from (rho^x, u^p of the object, S^p) (Sec. 3.2);
 //   - TRACK: each solid link adds the momentum -(f_i(x) + f+_opp(i)(x)) c_i
@@ -301,29 +301,13 @@ __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t ce
       }
     }
   }
-  if (b & (BIT_INFLOW | BIT_OUTFLOW)) {
-    const bool in = (b & BIT_INFLOW) != 0;
-    const int cx = in ? 1 : -1;
+  if (b & BIT_INFLOW) {
     float Ain[NA];
-    if (in) source_coeffs<FMT>(a, cell, true, Ain);
-    const uint32_t ximg = in ? uint32_t(nx - 1) : 0u;  // the periodic image the fluid pass pulled from
-    for (int cz = -1; cz <= 1; ++cz) {
-      for (int cy = -1; cy <= 1; ++cy) {
-        const uint32_t yzo =
-            uint32_t(nx) * (uint32_t(wrap_step(y, -cy, ny)) + uint32_t(ny) * uint32_t(wrap_step(z, -cz, nz)));
-        float As[NA];
-        source_coeffs<FMT>(a, ximg + yzo, false, As);
-        const float fold = eval_link(As, cx, cy, cz);
-        float fnew;
-        if (in) {
-          fnew = eval_link(Ain, cx, cy, cz);
-        } else {  // zero gradient: the face cell (nx - 1, y - cy, z - cz)
-          source_coeffs<FMT>(a, uint32_t(nx - 1) + yzo, false, As);
-          fnew = eval_link(As, cx, cy, cz);
-        }
-        add_link(m, cx, cy, cz, fnew - fold);
-      }
-    }
+    source_coeffs<FMT>(a, cell, true, Ain);
+#pragma unroll
+    for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+      for (int cy = -1; cy <= 1; ++cy) add_link(m, 1, cy, cz, eval_link(Ain, 1, cy, cz));
   }
   const float j[3] = {m[1], m[2], m[3]};
   const float P[6] = {m[4], m[5], m[6], m[7], m[8], m[9]};

@@ -28,8 +28,12 @@
 // numbered segment-major, tile-minor (x fastest) and the workgroups of one
 // XCD (round-robin dispatch) take consecutive numbers, so each XCD works on a
 // compact band of tiles.  The host picks the tile height and S from the
-// domain shape.  Every axis is treated as periodic here; faces and walls are
-// overwritten afterwards by the boundary pass.
+// domain shape.  Every axis is treated as periodic here, except that with
+// open x faces the column beyond x = nx - 1 is a copy of x = nx - 1 (so the
+// links leaving the outflow face are the zero-gradient ones already) and the
+// column before x = 0 sends nothing (so the inflow face's entering links
+// hold zero, replaced by the boundary pass without reading their periodic
+// image).  Walls and the inflow are applied afterwards by the boundary pass.
 #include "lbm_codec.h"
 
 #include <algorithm>
@@ -187,7 +191,10 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     }
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
-    const int xw = wrapi(gx, nx), yw = wrapi(gy, ny);
+    // open x faces (not in the mixed pipeline, which keeps the periodic pull)
+    const bool ghost_out = !MIXED && a.g.inflow && gx == nx;
+    const bool ghost_in = !MIXED && a.g.inflow && gx == -1;
+    const int xw = ghost_out ? nx - 1 : wrapi(gx, nx), yw = wrapi(gy, ny);
     const uint32_t row = uint32_t(xw) + uint32_t(nx) * uint32_t(yw);
     const bool own = compute && gx < nx && gy < ny;
 
@@ -294,7 +301,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
         } else if (active) {
           if (side == 0) {
 #pragma unroll
-            for (int h = 0; h < 9; ++h) L.lx[2 * h][r - 1][0] = xp[h];
+            for (int h = 0; h < 9; ++h) L.lx[2 * h][r - 1][0] = ghost_in ? 0.0f : xp[h];
           } else {
 #pragma unroll
             for (int h = 0; h < 9; ++h) L.lx[2 * h + 1][r - 1][RW + 1] = xm[h];
