@@ -303,10 +303,11 @@ __device__ inline float link_dot(const float g[10], int cx, int cy, int cz) {
   return gf;
 }
 
-// The boundary pass takes a listed fluid cell's fluid-pass result and adds,
-// per changed link, (new - pulled) distribution.  The fluid adjoint already
-// carries the pulled part (it is the fluid pass's own dependence, the solid
-// sources' share being discarded at those cells).  What remains:
+// The adjoint writes the step as a fully periodic pull plus, at each listed
+// fluid cell, (new - pulled) distribution on every changed link (the same
+// function as the forward passes, whatever share of the faces the forward
+// fluid pass takes on itself).  The fluid adjoint carries the periodic pull
+// (the solid sources' share being discarded at those cells).  What remains:
 //   - bounce-back link i of x: + f+_opp(i)(x), through x's own coefficients;
 //     the pulled rest state is a constant;
 //   - inflow link of x (cx = 1): + f+_i with x's inflow coefficients, - f+_i of
