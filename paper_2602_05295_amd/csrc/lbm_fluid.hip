@@ -29,7 +29,7 @@
 // XCD (round-robin dispatch) take consecutive numbers, so each XCD works on a
 // compact band of tiles.  The host picks the tile height and S from the
 // domain shape.  Every axis is treated as periodic here, except that with
-// open x faces the column beyond x = nx - 1 is a copy of x = nx - 1 (so the
+// open x faces (FACES) the column beyond x = nx - 1 is a copy of x = nx - 1 (so the
 // links leaving the outflow face are the zero-gradient ones already) and the
 // column before x = 0 sends nothing (so the inflow face's entering links
 // hold zero, replaced by the boundary pass without reading their periodic
@@ -141,7 +141,7 @@ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v -
 // MIXED: the stream pass of the paper's mixed-precision pipeline (Sec. 5.3):
 // the codes hold post-collision moments, which are reconstructed without a
 // collision, and the new moments are stored as FP32 post-stream moments.
-template <int FMT, int TYR, bool FORCE, bool MIXED = false, bool STREAM = false>
+template <int FMT, int TYR, bool FORCE, bool MIXED = false, bool STREAM = false, bool FACES = false>
 __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg, int zt, int ntail) {
   constexpr int OUT = MIXED ? int(FMT_F32) : FMT;
   constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
@@ -191,9 +191,9 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     }
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
-    // open x faces (not in the mixed pipeline, which keeps the periodic pull)
-    const bool ghost_out = !MIXED && a.g.inflow && gx == nx;
-    const bool ghost_in = !MIXED && a.g.inflow && gx == -1;
+    // open x faces (FACES; not in the mixed pipeline, which keeps the periodic pull)
+    const bool ghost_out = FACES && gx == nx;
+    const bool ghost_in = FACES && gx == -1;
     const int xw = ghost_out ? nx - 1 : wrapi(gx, nx), yw = wrapi(gy, ny);
     const uint32_t row = uint32_t(xw) + uint32_t(nx) * uint32_t(yw);
     const bool own = compute && gx < nx && gy < ny;
@@ -396,25 +396,25 @@ int device_cus() {
   return cached[dev];
 }
 
-template <int FMT, bool FORCE, bool MIXED = false, bool STREAM = false>
+template <int FMT, bool FORCE, bool MIXED = false, bool STREAM = false, bool FACES = false>
 hipError_t launch_rows(const FluidPlan& c, const StepParams& p, hipStream_t s) {
   const dim3 grid(uint32_t(c.nwg));
   const int zt = p.g.nz - c.tail;
   switch (c.rows) {
     case 8:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED, STREAM>), grid, dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 8, FORCE, MIXED, STREAM, FACES>), grid, dim3(11 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
     case 10:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED, STREAM>), grid, dim3(13 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 10, FORCE, MIXED, STREAM, FACES>), grid, dim3(13 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
     case 12:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED, STREAM>), grid, dim3(15 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 12, FORCE, MIXED, STREAM, FACES>), grid, dim3(15 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
     default:
-      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED, STREAM>), grid, dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
+      hipLaunchKernelGGL((fluid_kernel<FMT, 13, FORCE, MIXED, STREAM, FACES>), grid, dim3(16 * RW), 0, s, p, c.ntx, c.nty, c.nseg,
                          c.nwg, zt, c.ntail);
       break;
   }
@@ -525,16 +525,23 @@ hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s) {
 hipError_t launch_fluid(int fmt, const StepParams& p, int rows, hipStream_t s) {
   const FluidPlan c = fluid_plan(p.g, rows, device_cus());
   if (c.rows == 0) return hipErrorInvalidValue;
-  // a body force takes the plain stores (force runs are the small ones)
-  if (fmt == FMT_F32)
-    return p.force ? launch_rows<FMT_F32, true>(c, p, s)
-                   : (p.stream_out ? launch_rows<FMT_F32, false, false, true>(c, p, s)
-                                   : launch_rows<FMT_F32, false>(c, p, s));
+  // A body force takes the plain stores (force runs are the small ones).
+  // Open faces have kernels of their own, so the periodic ones carry none of
+  // the face logic (it cost them 1% on 256^3).
   hipError_t e = hipErrorInvalidValue;
-  dispatch_codes(fmt, [&]<int F>() {
-    e = p.force ? launch_rows<F, true>(c, p, s)
-                : (p.stream_out ? launch_rows<F, false, false, true>(c, p, s) : launch_rows<F, false>(c, p, s));
-  });
+  auto go = [&]<int F>() {
+    if (p.g.inflow)
+      e = p.force ? launch_rows<F, true, false, false, true>(c, p, s)
+                  : (p.stream_out ? launch_rows<F, false, false, true, true>(c, p, s)
+                                  : launch_rows<F, false, false, false, true>(c, p, s));
+    else
+      e = p.force ? launch_rows<F, true>(c, p, s)
+                  : (p.stream_out ? launch_rows<F, false, false, true>(c, p, s) : launch_rows<F, false>(c, p, s));
+  };
+  if (fmt == FMT_F32)
+    go.template operator()<FMT_F32>();
+  else
+    dispatch_codes(fmt, go);
   return e;
 }
 
