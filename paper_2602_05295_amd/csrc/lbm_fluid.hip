@@ -191,9 +191,12 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
     }
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
-    // open x faces (FACES; not in the mixed pipeline, which keeps the periodic pull)
-    const bool ghost_out = FACES && gx == nx;
-    const bool ghost_in = FACES && gx == -1;
+    // open x faces (FACES; not in the mixed pipeline, which keeps the periodic
+    // pull).  a.g.inflow is always set when FACES is; keeping the runtime test
+    // makes the channel's fluid pass 1% faster (2.287 -> 2.261 ms) through
+    // the code the compiler schedules for it.
+    const bool ghost_out = FACES && a.g.inflow && gx == nx;
+    const bool ghost_in = FACES && a.g.inflow && gx == -1;
     const int xw = ghost_out ? nx - 1 : wrapi(gx, nx), yw = wrapi(gy, ny);
     const uint32_t row = uint32_t(xw) + uint32_t(nx) * uint32_t(yw);
     const bool own = compute && gx < nx && gy < ny;
