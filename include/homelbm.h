@@ -131,8 +131,8 @@ typedef struct lbm_options {
 int lbm_default_options(lbm_options* opt);
 
 /*
- * Creates a context for an nx*ny*nz grid (dims[0..2] = nx, ny, nz, each >= 1,
- * nx*ny*nz <= 2^30).  tau > 1/2 is the relaxation time of App. A (kinematic
+ * Creates a context for an nx*ny*nz grid (dims[0..2] = nx, ny, nz, each in
+ * 1..65535, nx*ny*nz <= 2^30).  tau > 1/2 is the relaxation time of App. A (kinematic
  * viscosity nu = (tau - 1/2)/3).  solid_mask is a host array of nx*ny*nz bytes,
  * 0 = fluid, 1..255 = solid, the value naming the object the cell belongs to
  * (lbm_set_object), or NULL for no solids; it is copied.  moment_format is
@@ -262,8 +262,8 @@ int lbm_check(lbm_ctx* ctx, uint64_t* bad);
  * It follows the same step as lbm_step: App. A collision, the third-order
  * reconstruction of Eq. (three_order_f), pull streaming, projection, and the
  * boundary rules (bounce-back, inflow, outflow).  Asynchronous on the context
- * stream.  Contributions through boundary cells are added with float atomics,
- * so the last bits can vary between runs.
+ * stream.  Every output cell is written by one thread (boundary contributions
+ * are gathered, not scattered), so the result is the same on every run.
  */
 int lbm_adjoint_step(lbm_ctx* ctx, const float* m_t, const float* lam_next, float* lam_prev);
 
@@ -279,12 +279,6 @@ int lbm_equilibrium_vjp(lbm_ctx* ctx, const float* rho, const float* u, const fl
 int lbm_synchronize(lbm_ctx* ctx);
 
 /*
- * Runs n steps like lbm_step while timing every kernel launch with HIP events
- * on the context stream; returns the summed device time (ms) of the fluid
- * passes and of the boundary passes, and the number of launches of each.
- * Synchronises.
- */
-/*
  * Runs n steps like lbm_step, timing each stage with HIP events on the
  * context stream: ms[0] the fluid (or stream) pass, ms[1] the boundary pass
  * (or the link corrections), ms[2] the requantize pass of pipeline 1 (0
@@ -292,6 +286,12 @@ int lbm_synchronize(lbm_ctx* ctx);
  */
 int lbm_profile_stages(lbm_ctx* ctx, int n, double ms[3]);
 
+/*
+ * Runs n steps like lbm_step while timing every kernel launch with HIP events
+ * on the context stream; returns the summed device time (ms) of the fluid
+ * passes and of the boundary passes, and the number of launches of each.
+ * Synchronises.
+ */
 int lbm_profile_steps(lbm_ctx* ctx, int n, double* fluid_ms, double* boundary_ms, int* fluid_launches,
                       int* boundary_launches);
 

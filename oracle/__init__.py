@@ -112,6 +112,8 @@ def lib():
         L.orc_dither.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, _dp, _u32]
         L.orc_encode_one.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
         L.orc_encode_one.restype = ctypes.c_uint32
+        L.orc_encode_one_b.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.orc_encode_one_b.restype = ctypes.c_uint32
         L.orc_decode_one.argtypes = [ctypes.c_uint32, ctypes.c_int]
         L.orc_decode_one.restype = ctypes.c_double
         L.orc_q16_encode.argtypes = [_dp, _u8, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, _u32]
@@ -351,6 +353,11 @@ def dither(idx: int, t: int, seed: int, mode: int = 1):
 
 def encode_one(m: float, k: int, xi: float = 0.0) -> int:
     return int(lib().orc_encode_one(float(m), int(k), float(xi)))
+
+
+def qb_encode_one(m: float, k: int, xi: float, b: int) -> int:
+    """The b-bit code of one codec variable (R18 ranges and rounding)."""
+    return int(lib().orc_encode_one_b(float(m), int(k), float(xi), int(b)))
 
 
 def decode_one(q: int, k: int) -> float:

@@ -47,6 +47,10 @@
 //       The face rule is applied before the solid rule.
 //   R12 Body force: the stored momentum includes F/2 (Eq. rho_u_stress) and
 //       the collision follows App. A with its force terms.
+//   R15 The encode decision q = floor(m' (2^b - 1) + 1/2 + xi) is taken in
+//       double precision from the double-precision step, half-way values
+//       rounding up, as printed.  (A single-precision implementation meets
+//       the same decision to within one code.)
 //   R16 Wall rule 1 (the solid coupling of Sec. 3.2 on a voxel mask): the
 //       link from fluid x to its solid source s = x - c_i meets the solid at
 //       the link midpoint p = x - c_i/2; f_i(x) = h_i(rho^p, u^p, S^p) with
@@ -386,20 +390,14 @@ void dither(uint32_t idx, uint32_t t, uint32_t seed, int mode, double xi[10], ui
   }
 }
 
-// q = floor(m' (2^b - 1) + 1/2 + xi), m' = (m - min)/(max - min), saturated
-// (R5).  The decision is taken in single precision, the precision the GPU
-// library stores and computes in, as q = rint(m' (2^b - 1) + xi) with exact
-// ties to even (R15): single precision puts m' (2^b - 1) on a grid of 1/512
-// or 1/256 of a step and the dither on a grid of 1/128, so exact ties occur
-// about once in 512 encodes, and sending them all up would add a systematic
-// +1/1024 step per encode, the bias the dither is there to remove.
+// q = floor(m' (2^b - 1) + 1/2 + xi), m' = (m - min)/(max - min), taken in
+// double precision exactly as Sec. 5.3 writes it (half-way values go up), and
+// saturated (R5).
 uint16_t encode_one(double m, int k, double xi) {
-  const float mf = float(m);
-  const float lo = float(Q_LO[k]);
-  const float scale = float(double(QMAX) / (Q_HI[k] - Q_LO[k]));
-  const float v = std::nearbyint((mf - lo) * scale + float(xi));  // default rounding: to nearest, ties to even
-  if (!(v >= 0.0f)) return 0;  // also maps NaN to 0
-  if (v >= float(QMAX)) return uint16_t(QMAX);
+  const double mp = (m - Q_LO[k]) / (Q_HI[k] - Q_LO[k]);
+  const double v = std::floor(mp * double(QMAX) + 0.5 + xi);
+  if (!(v >= 0.0)) return 0;  // also maps NaN to 0
+  if (v >= double(QMAX)) return uint16_t(QMAX);
   return uint16_t(v);
 }
 
@@ -464,12 +462,10 @@ struct Bits {
 
 uint32_t encode_one_b(double m, int k, double xi, int b) {
   const uint32_t qmax = (1u << b) - 1u;
-  const float mf = float(m);
-  const float lo = float(Q_LO[k]);
-  const float scale = float(double(qmax) / (Q_HI[k] - Q_LO[k]));
-  const float v = std::nearbyint((mf - lo) * scale + float(xi));  // ties to even (R15)
-  if (!(v >= 0.0f)) return 0;
-  if (v >= float(qmax)) return qmax;
+  const double mp = (m - Q_LO[k]) / (Q_HI[k] - Q_LO[k]);
+  const double v = std::floor(mp * double(qmax) + 0.5 + xi);
+  if (!(v >= 0.0)) return 0;
+  if (v >= double(qmax)) return qmax;
   return uint32_t(v);
 }
 
@@ -736,6 +732,7 @@ void orc_dither(uint32_t idx, uint32_t t, uint32_t seed, int mode, double* xi10,
 }
 
 uint32_t orc_encode_one(double m, int k, double xi) { return encode_one(m, k, xi); }
+uint32_t orc_encode_one_b(double m, int k, double xi, int b) { return encode_one_b(m, k, xi, b); }
 double orc_decode_one(uint32_t q, int k) { return decode_one(q, k); }
 
 // Encode a field of stored moments (10 planes) into 5 planes of words.

@@ -399,7 +399,8 @@ int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_
   *out = nullptr;
   if (!dims) return fail(nullptr, LBM_ERR_INVALID_ARG, "dims is NULL");
   for (int a = 0; a < 3; ++a)
-    if (dims[a] < 1) return fail(nullptr, LBM_ERR_INVALID_ARG, "every dimension must be >= 1");
+    if (dims[a] < 1 || dims[a] > 65535)
+      return fail(nullptr, LBM_ERR_INVALID_ARG, "every dimension must be in [1, 65535]");
   const int64_t N = int64_t(dims[0]) * dims[1] * dims[2];
   if (N > (int64_t(1) << 30)) return fail(nullptr, LBM_ERR_INVALID_ARG, "nx*ny*nz must be <= 2^30");
   if (!(tau > 0.5) || !std::isfinite(tau)) return fail(nullptr, LBM_ERR_INVALID_ARG, "tau must be > 1/2");

@@ -44,6 +44,11 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     dims = (ctypes.c_int * 3)(4, 4, 4)
     assert L.lbm_create(dims, 0.5, None, 0, ctypes.byref(h)) == homelbm.ERR_INVALID_ARG
     assert L.lbm_create(dims, 0.6, None, 7, ctypes.byref(h)) == homelbm.ERR_INVALID_ARG
+    # boundary-list entries hold y and z in 16 bits each: larger axes are refused
+    for d in [(65536, 2, 2), (2, 65536, 2), (2, 2, 70000)]:
+        dims = (ctypes.c_int * 3)(*d)
+        assert L.lbm_create(dims, 0.6, None, 0, ctypes.byref(h)) == homelbm.ERR_INVALID_ARG
+        assert b"65535" in L.lbm_last_error(None)
     assert h.value is None
 
 

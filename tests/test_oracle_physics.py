@@ -338,3 +338,125 @@ def test_mixed_q16_step_keeps_rest_and_mass(orc):
     out, m_ps = orc.mixed_q16_step(P, w, t=1, seed=3, mode=1)
     for k in range(4):
         assert abs(m_ps[k].sum() - post[k].sum()) < 1e-10 * max(1.0, abs(post[k].sum()))
+
+
+# ---------------------------------------------------------- open faces (R11) --
+
+def test_outflow_of_an_x_invariant_field_is_the_periodic_step(orc):
+    """A field that does not depend on x has a zero x-gradient everywhere, so
+    the zero-gradient outflow face must pull exactly what the periodic step
+    pulls: f_i(nx-1, y, z) = f+_i(nx-1, y - c_y, z - c_z) for c_x = -1.  Cells
+    x >= 1 pull nothing from the inflow rule either, so every cell but the
+    inflow plane matches the periodic step.  The field has (y, z) structure in
+    every moment, so a source without the transverse shift fails."""
+    nx, ny, nz = 6, 7, 5
+    g = W.random_moments(1, ny, nz, seed=21, dj=0.04, dp=0.004)       # (10, nz, ny, 1)
+    m = np.ascontiguousarray(np.broadcast_to(g, (10, nz, ny, nx)))
+    for inflow_u in ((0.06, 0.0, 0.0), (0.03, 0.01, -0.02)):
+        Po = orc.make_params((nx, ny, nz), 0.57, inflow=True, u_in=inflow_u)
+        Pp = orc.make_params((nx, ny, nz), 0.57)
+        open_ = orc.step(Po, m)
+        per = orc.step(Pp, m)
+        assert np.abs(open_[..., 1:] - per[..., 1:]).max() < 1e-14
+        # and the inflow plane does differ: the inflow rule is in force
+        assert np.abs(open_[..., 0] - per[..., 0]).max() > 1e-4
+
+
+@pytest.mark.parametrize("tau", [0.53, 0.8])
+def test_inflow_keeps_a_uniform_state_with_stress(orc, tau):
+    """A uniform state whose velocity equals u_in, with a non-equilibrium
+    stress, must map to its own collision at every cell, face cells included:
+    the inflow's moment boundary S^p = u_in u_in + (S^x - u^x u^x) then
+    rebuilds exactly the cell's post-collision distribution (Sec. 3.2), and
+    the outflow's zero gradient copies it.  Dropping the non-equilibrium
+    carry-over changes the inflow cells."""
+    n = (5, 4, 3)
+    u = np.array([0.07, -0.01, 0.02])
+    rho = 1.03
+    Sneq = np.array([[2e-3, 1e-3, -5e-4], [1e-3, -1e-3, 3e-4], [-5e-4, 3e-4, 4e-4]])
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    S = np.outer(u, u) + Sneq
+    m = np.zeros((10,) + n[::-1])
+    m[0] = rho
+    m[1:4] = (rho * u)[:, None, None, None]
+    for p, (a, b) in enumerate(pairs):
+        m[4 + p] = rho * S[a, b]
+    post = orc.collide(rho, u, [S[a, b] for a, b in pairs], tau)
+    want = np.r_[post[0], post[0] * post[1:4], post[0] * post[4:]]
+    Po = orc.make_params(n, tau, inflow=True, u_in=u)
+    out = orc.step(Po, m)
+    assert np.abs(out - want[:, None, None, None]).max() < 1e-15
+    # the same field with the wrong inflow velocity is not kept
+    Pw = orc.make_params(n, tau, inflow=True, u_in=u + np.array([0.01, 0, 0]))
+    assert np.abs(orc.step(Pw, m)[..., 0] - want[:, None, None]).max() > 1e-4
+
+
+def test_open_channel_settles_to_the_inflow(orc):
+    """An obstacle-free channel with periodic y, z started at rest: once the
+    start-up transient has left, the mass flux through the inflow plane equals
+    the flux through the outflow plane and the inflow plane moves at u_in."""
+    n = (32, 4, 4)
+    u_in = 0.05
+    m = orc.equilibrium_moments(np.ones(n[::-1]), np.zeros((3,) + n[::-1]))
+    P = orc.make_params(n, 0.8, inflow=True, u_in=(u_in, 0, 0))
+    for _ in range(3000):
+        m = orc.step(P, m)
+    jx = m[1].mean(axis=(0, 1))
+    ux = (m[1] / m[0]).mean(axis=(0, 1))
+    assert abs(jx[0] - jx[-1]) / jx[0] < 1e-3, (jx[0], jx[-1])
+    assert abs(ux[0] - u_in) / u_in < 1e-3, ux[0]
+    assert np.abs(m[2:4]).max() < 1e-15
+
+
+# ----------------------------------------------------- body force (App. A) --
+
+def _d3q27():
+    c = np.array([(x, y, z) for z in (-1, 0, 1) for y in (-1, 0, 1) for x in (-1, 0, 1)], float)
+    w1 = {-1: 1 / 6, 0: 2 / 3, 1: 1 / 6}
+    w = np.array([w1[int(a)] * w1[int(b)] * w1[int(g)] for a, b, g in c])
+    return c, w
+
+
+def _guo_bgk(f, F, tau):
+    """One BGK collision with Guo's forcing term, written on the 27
+    distributions (Guo, Zheng & Shi, Phys. Rev. E 65, 046308 (2002)):
+    f+ = f - (f - f_eq)/tau + (1 - 1/(2 tau)) w [(c - u)/cs^2 + (c.u) c/cs^4].F,
+    u = (sum c f + F/2)/rho, f_eq the second-order Hermite equilibrium."""
+    c, w = _d3q27()
+    rho = f.sum()
+    u = (c.T @ f + F / 2) / rho
+    cu = c @ u
+    feq = rho * w * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * u @ u)
+    src = w * (3 * ((c - u) @ F) + 9 * cu * (c @ F))
+    return f - (f - feq) / tau + (1 - 1 / (2 * tau)) * src
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.7, 1.6])
+def test_forced_collision_is_guo_forcing_in_moments(orc, tau):
+    """App. A's forced collision equals the moments of a distribution-level
+    collision with Guo's forcing: the shear part (off-diagonal entries and
+    the deviator of the diagonal) at rate 1/tau, the trace at rate 1 (R8),
+    and the momentum rho u + F/2 after the collision.  Each force term of
+    App. A is pinned away from tau = 1."""
+    c, w = _d3q27()
+    rng = np.random.default_rng(int(100 * tau))
+    H2 = np.einsum("ia,ib->iab", c, c) - np.eye(3) / 3
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    for _ in range(6):
+        f = w * (1 + 0.3 * rng.standard_normal(27))               # arbitrary positive set
+        F = 1e-2 * rng.standard_normal(3)
+        rho = f.sum()
+        u = (c.T @ f + F / 2) / rho                             # stored j includes F/2
+        Pi = np.einsum("i,iab->ab", f, H2)
+        out = orc.collide(rho, u, [Pi[a, b] / rho for a, b in pairs], tau, F)
+        Splus = np.zeros((3, 3))
+        for p, (a, b) in enumerate(pairs):
+            Splus[a, b] = Splus[b, a] = out[4 + p]
+        g_shear = _guo_bgk(f, F, tau)
+        g_bulk = _guo_bgk(f, F, 1.0)
+        Pi_s = np.einsum("i,iab->ab", g_shear, H2)
+        Pi_b = np.einsum("i,iab->ab", g_bulk, H2)
+        dev = lambda A: A - np.trace(A) / 3 * np.eye(3)
+        assert np.abs(dev(rho * Splus) - dev(Pi_s)).max() < 1e-15
+        assert abs(np.trace(rho * Splus) - np.trace(Pi_b)) < 1e-15
+        assert np.abs(rho * out[1:4] - c.T @ g_shear).max() < 1e-15
