@@ -268,6 +268,23 @@ int lbm_check(lbm_ctx* ctx, uint64_t* bad);
 int lbm_adjoint_step(lbm_ctx* ctx, const float* m_t, const float* lam_next, float* lam_prev);
 
 /*
+ * lbm_adjoint_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same kernels and result, with the per-cell flags the
+ * adjoint passes read kept in a fixed 32 MiB device array of the library
+ * (one per GPU, held until the process ends) instead of a buffer the context
+ * allocates on first use.  It calls no hipMalloc, hipFree or other
+ * allocating routine.  Arguments, layout and errors as lbm_adjoint_step,
+ * plus LBM_ERR_INVALID_ARG when nx*ny*nz exceeds 33,554,432 (the array's
+ * size) or when the boundary list still has to be rebuilt after an inflow
+ * change (any lbm_step, lbm_step_into or lbm_adjoint_step rebuilds it).
+ * Every call on a GPU rewrites the whole flag array for its context, so calls
+ * on one GPU that overlap in time (on different streams or host threads)
+ * race and must be ordered by the caller.
+ */
+int lbm_adjoint_step_noalloc(lbm_ctx* ctx, const float* m_t, const float* lam_next, float* lam_prev);
+
+/*
  * Vector-Jacobian product of lbm_set_equilibrium's map (rho, u) -> (rho, rho u,
  * rho u u): given lam (ten planes), writes grad_rho (one plane; may be NULL)
  * and grad_u (three planes); zero at solid cells.  Device pointers, async.

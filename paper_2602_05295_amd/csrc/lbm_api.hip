@@ -6,6 +6,7 @@
 #include <cmath>
 #include <iterator>
 #include <cstdio>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <string>
@@ -394,6 +395,10 @@ int lbm_default_options(lbm_options* o) {
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
+namespace {
+int scratch_device_ptr(lbm_ctx* c, uint8_t** out);
+}
+
 int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_ctx** out) {
   if (!out) return fail(nullptr, LBM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -452,6 +457,11 @@ int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_
     lbm_destroy(c);
     return r;
   }
+  // set-up of the allocation-free adjoint: the device address of its scratch
+  // array on this device, taken here, before any caller starts a capture
+  uint8_t* ignored = nullptr;
+  (void)scratch_device_ptr(c, &ignored);  // a failure is reported by lbm_adjoint_step_noalloc itself
+  c->err.clear();
   *out = c;
   return LBM_OK;
 }
@@ -792,7 +802,8 @@ int lbm_profile_steps(lbm_ctx* c, int n, double* fluid_ms, double* boundary_ms, 
   return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float* lam_prev) {
+namespace {
+int adjoint_args_ok(lbm_ctx* c, const float* m_t, const float* lam_next, float* lam_prev) {
   if (!c || !m_t || !lam_next || !lam_prev) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
   if (c->fmt != FMT_F32) return fail(c, LBM_ERR_UNSUPPORTED, "the adjoint step needs FP32 moments");
   if (c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f)
@@ -801,8 +812,33 @@ int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float*
   if (static_cast<const void*>(lam_prev) == static_cast<const void*>(lam_next) ||
       static_cast<const void*>(lam_prev) == static_cast<const void*>(m_t))
     return fail(c, LBM_ERR_INVALID_ARG, "lam_prev must not alias lam_next or m_t");
+  return LBM_OK;
+}
+
+// The adjoint passes over the cell flags `flags` (1 listed fluid, 2 solid, 0 other).
+int adjoint_launch(lbm_ctx* c, const uint8_t* flags, const float* m_t, const float* lam_next, float* lam_prev) {
+  AdjParams p{};
+  const size_t P = size_t(c->N);
+  for (int k = 0; k < 10; ++k) {
+    p.lam_in[k] = lam_next + k * P;
+    p.m[k] = m_t + k * P;
+    p.lam_out[k] = lam_prev + k * P;
+  }
+  p.flags = flags;
+  p.g = geom(c);
+  p.om1 = float(1.0 - 1.0 / c->tau);
+  for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
+  const hipError_t e = launch_adjoint(p, c->opt.tile_rows, c->d_cells, c->d_bits, int(c->n_fluid_b), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+  return LBM_OK;
+}
+}  // namespace
+
+int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float* lam_prev) {
+  int r = adjoint_args_ok(c, m_t, lam_next, lam_prev);
+  if (r != LBM_OK) return r;
   if (!c->list_built) {
-    const int r = build_list(c);
+    r = build_list(c);
     if (r != LBM_OK) return r;
   }
   hipError_t e = hipSuccess;
@@ -814,20 +850,60 @@ int lbm_adjoint_step(lbm_ctx* c, const float* m_t, const float* lam_next, float*
     if (e != hipSuccess) return hip_fail(c, e, "adjoint flags");
     c->flags_valid = true;
   }
-  AdjParams p{};
-  const size_t P = size_t(c->N);
-  for (int k = 0; k < 10; ++k) {
-    p.lam_in[k] = lam_next + k * P;
-    p.m[k] = m_t + k * P;
-    p.lam_out[k] = lam_prev + k * P;
+  return adjoint_launch(c, c->d_flags, m_t, lam_next, lam_prev);
+}
+
+// ------------------------------------------------ allocation-free adjoint ---
+// lbm_adjoint_step_noalloc keeps the cell flags (one byte per cell) in this
+// fixed device array instead of the context's lazily allocated buffer.  Each
+// device holds its own copy until the process ends.  Host code never passes
+// the array's name to a kernel: it uses the device address taken once per
+// device with hipGetSymbolAddress (scratch_device_ptr).
+constexpr size_t kAdjointScratchBytes = size_t(32) << 20;  // cells of one context at most
+static __device__ __align__(256) uint8_t scratch[kAdjointScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};  // per device: the address of `scratch`
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device (lbm_create primes it).
+int scratch_device_ptr(lbm_ctx* c, uint8_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(c, LBM_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
   }
-  p.flags = c->d_flags;
-  p.g = geom(c);
-  p.om1 = float(1.0 - 1.0 / c->tau);
-  for (int a = 0; a < 3; ++a) p.u_in[a] = c->opt.u_in[a];
-  e = launch_adjoint(p, c->opt.tile_rows, c->d_cells, c->d_bits, int(c->n_fluid_b), c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+  *out = static_cast<uint8_t*>(g_scratch_dev[dev]);
   return LBM_OK;
+}
+}  // namespace
+
+int lbm_adjoint_step_noalloc(lbm_ctx* c, const float* m_t, const float* lam_next, float* lam_prev) {
+  int r = adjoint_args_ok(c, m_t, lam_next, lam_prev);
+  if (r != LBM_OK) return r;
+  if (!c->list_built)
+    return fail(c, LBM_ERR_INVALID_ARG,
+                "the boundary list is not built (it is rebuilt by the first lbm_step, lbm_step_into or "
+                "lbm_adjoint_step after the inflow setting changes)");
+  if (size_t(c->N) > kAdjointScratchBytes)
+    return fail(c, LBM_ERR_INVALID_ARG,
+                "lbm_adjoint_step_noalloc takes at most " + std::to_string(kAdjointScratchBytes) +
+                    " cells (nx*ny*nz = " + std::to_string(c->N) + "); use lbm_adjoint_step");
+  uint8_t* flags = nullptr;
+  r = scratch_device_ptr(c, &flags);
+  if (r != LBM_OK) return r;
+  // every one of the N flags is written, so nothing of an earlier call survives
+  const hipError_t e =
+      launch_adjoint_flags(c->d_mask, c->N, c->d_cells, c->d_bits, int(c->n_fluid_b + c->n_solid_b), flags, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint flags");
+  return adjoint_launch(c, flags, m_t, lam_next, lam_prev);
 }
 
 int lbm_equilibrium_vjp(lbm_ctx* c, const float* rho, const float* u, const float* lam, float* grad_rho,

@@ -136,6 +136,7 @@ def lib():
     L.lbm_profile_steps.argtypes = [vp, i, P(ctypes.c_double), P(ctypes.c_double), P(i), P(i)]
     L.lbm_debug_dither.argtypes = [i, vp, ctypes.c_uint32, ctypes.c_uint32, i, vp]
     L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
+    L.lbm_adjoint_step_noalloc.argtypes = [vp, vp, vp, vp]
     L.lbm_equilibrium_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_fluid_plan.argtypes = [P(i), i, i, P(i)]
     # batched API
