@@ -53,21 +53,35 @@ class Params(ctypes.Structure):
         ("u_in", ctypes.c_double * 3),
         ("wall_rule", ctypes.c_int),
         ("objects", ctypes.POINTER(ctypes.c_double)),
+        ("tris", ctypes.POINTER(ctypes.c_float)),
+        ("ntris", ctypes.c_int64),
+        ("tri_obj", ctypes.POINTER(ctypes.c_uint8)),
     ]
 
 
 def make_params(dims, tau, F=(0.0, 0.0, 0.0), inflow=False, u_in=(0.0, 0.0, 0.0), literal_xyz=False,
-                wall_rule=0, objects=None) -> Params:
+                wall_rule=0, objects=None, triangles=None, tri_obj=None) -> Params:
     """objects: None or a (256, 9) array, row id = center C, velocity V,
-    angular velocity W of the solid object with mask value id (R16, R17)."""
+    angular velocity W of the solid object with mask value id (R16, R17).
+    triangles (T, 9) float32 and tri_obj (T,) uint8: the obstacle meshes of
+    wall rule 2 (R26)."""
     nx, ny, nz = (int(d) for d in dims)
     P = Params(nx, ny, nz, int(bool(inflow)), int(bool(literal_xyz)), float(tau),
                (ctypes.c_double * 3)(*[float(v) for v in F]),
-               (ctypes.c_double * 3)(*[float(v) for v in u_in]), int(wall_rule), None)
+               (ctypes.c_double * 3)(*[float(v) for v in u_in]), int(wall_rule), None, None, 0, None)
     if objects is not None:
         obj = np.ascontiguousarray(objects, dtype=np.float64).reshape(256, 9)
         P.object_table = obj  # keeps the table alive as long as the params
         P.objects = obj.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if triangles is not None:
+        tr = np.ascontiguousarray(triangles, dtype=np.float32).reshape(-1, 9)
+        ob = np.ascontiguousarray(tri_obj, dtype=np.uint8).reshape(-1)
+        if ob.size != tr.shape[0]:
+            raise ValueError("one object id per triangle")
+        P.tri_table, P.obj_table = tr, ob
+        P.tris = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        P.ntris = tr.shape[0]
+        P.tri_obj = ob.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     return P
 
 
@@ -94,6 +108,8 @@ def lib():
         L.orc_post_collision_f.argtypes = [_P(Params), _dp, _dp, _dp, _dp]
         L.orc_step.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int]
         L.orc_object_forces.argtypes = [_P(Params), _u8, _dp, _dp]
+        L.orc_mesh_links.argtypes = [_P(Params), _u8, _dp, ctypes.c_int64]
+        L.orc_mesh_links.restype = ctypes.c_int64
         L.orc_stream_post.argtypes = [_P(Params), _u8, _dp, _dp, ctypes.c_int]
         L.orc_collide_field.argtypes = [_P(Params), _u8, _dp, _dp]
         L.orc_mixed_q16_step.argtypes = [_P(Params), _u8, _u32, _u32, _dp, ctypes.c_uint32, ctypes.c_uint32,
@@ -140,7 +156,17 @@ def _mask_ptr(mask):
 
 
 def default_threads() -> int:
-    return max(1, min(16, os.cpu_count() or 1))
+    """OMP_NUM_THREADS when set, else the CPUs this process may run on."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    if n <= 0:
+        try:
+            n = len(os.sched_getaffinity(0))
+        except (AttributeError, OSError):
+            n = os.cpu_count() or 1
+    return max(1, n)
 
 
 # ---------------------------------------------------------------- lattice ---
@@ -254,6 +280,16 @@ def object_forces(params: Params, m, mask):
     return out
 
 
+def mesh_links(params: Params, mask):
+    """Every link of wall rule 2 (R26): array (n, 7) of cell index, direction
+    i, met a triangle (1/0), boundary point p (x, y, z), object id."""
+    mk, mp = _mask_ptr(mask)
+    n = lib().orc_mesh_links(ctypes.byref(params), mp, None, 0)
+    out = np.zeros((max(n, 1), 7))
+    lib().orc_mesh_links(ctypes.byref(params), mp, _ptr(out, _dp), n)
+    return out[:n]
+
+
 def run(params: Params, m, nsteps, mask=None, nthreads=None):
     for _ in range(nsteps):
         m = step(params, m, mask, nthreads)
@@ -293,18 +329,20 @@ def step_cells(params: Params, m, cells, mask=None, nthreads=None):
     return out
 
 
-def adjoint_step(params: Params, m_t, lam_next, mask=None):
-    """lam_prev = J(m_t)^T lam_next for one step."""
+def adjoint_step(params: Params, m_t, lam_next, mask=None, nthreads=None):
+    """lam_prev = J(m_t)^T lam_next for one step (the per-cell Jacobians on
+    nthreads threads)."""
     m_t = _check_field(m_t, params)
     lam_next = _check_field(lam_next, params)
     out = np.zeros_like(m_t)
     mk, mp = _mask_ptr(mask)
-    if lib().orc_adjoint_step(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), _ptr(out, _dp), 1) != 0:
+    nt = default_threads() if nthreads is None else int(nthreads)
+    if lib().orc_adjoint_step(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), _ptr(out, _dp), nt) != 0:
         raise ValueError("the oracle's adjoint follows bounce-back walls only (wall_rule 0)")
     return out
 
 
-def adjoint_step_cells(params: Params, m_t, lam_next, cells, mask=None):
+def adjoint_step_cells(params: Params, m_t, lam_next, cells, mask=None, nthreads=None):
     """lam_prev = J(m_t)^T lam_next at the given cells only, (ncells, 10):
     the same transpose as adjoint_step, gathered per source cell."""
     m_t = _check_field(m_t, params)
@@ -313,7 +351,8 @@ def adjoint_step_cells(params: Params, m_t, lam_next, cells, mask=None):
     out = np.zeros((cells.size, 10))
     mk, mp = _mask_ptr(mask)
     if lib().orc_adjoint_step_cells(ctypes.byref(params), mp, _ptr(m_t, _dp), _ptr(lam_next, _dp), cells.size,
-                                    _ptr(cells, _i64), _ptr(out, _dp), 1) != 0:
+                                    _ptr(cells, _i64), _ptr(out, _dp),
+                                    default_threads() if nthreads is None else int(nthreads)) != 0:
         raise ValueError("the oracle's adjoint follows bounce-back walls only (wall_rule 0)")
     return out
 

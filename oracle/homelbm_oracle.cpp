@@ -58,6 +58,16 @@
 //       value = object id, positions taken from x without wrapping) and
 //       S^p = u^p u^p + (S^x - u^x u^x), x's post-collision moments.  Wall
 //       rule 0 is R10.
+//   R26 Wall rule 2 (the solid coupling of Sec. 3.2 with the obstacles'
+//       triangle meshes, as the paper's per-triangle solid correction finds
+//       it): which links to replace is still decided by the mask (fluid x,
+//       solid s = x - c_i); p is the point where the link segment from x to
+//       x - c_i first meets a triangle (nearest to x, ties to the lowest
+//       triangle index, edges included), and u^p is taken there from the
+//       triangle's object.  A link that meets no triangle is not coupled: it
+//       keeps the pull from its resting solid source.  With objects at rest
+//       u^p = 0 wherever p lies, so where every solid link meets a mesh rules
+//       1 and 2 then agree.
 //   R18 Bit allocation b_rho_u / b_S: the codes of rho and u take b1 bits,
 //       those of N b2 bits (same ranges, rounding and dither), concatenated
 //       low bit first, rho, ux, uy, uz, Nxx, Nyy, Nzz, Nxy, Nxz, Nyz, into
@@ -72,6 +82,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #ifdef _OPENMP
@@ -221,9 +232,14 @@ struct OrcParams {
   double tau;
   double F[3];      // uniform body force
   double u_in[3];   // inflow velocity
-  int wall_rule;    // 0: halfway bounce-back (R10); 1: moment wall (R16)
+  int wall_rule;    // 0: halfway bounce-back (R10); 1: moment wall at the link
+                    // midpoint (R16); 2: moment wall where the link meets the
+                    // obstacle meshes (R26)
   const double* objects;  // 256 x 9: center C, velocity V, angular velocity W of
                           // object id (mask value); NULL: all at rest at 0
+  const float* tris;      // wall rule 2: ntris triangles, 9 floats each (x0 y0 z0 x1 ... z2)
+  int64_t ntris;
+  const uint8_t* tri_obj; // object id of each triangle
 };
 
 }  // extern "C"
@@ -235,15 +251,73 @@ inline int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
+// Triangles that may meet a link of each lattice point (wall rule 2): a
+// link from x has length at most sqrt(3) and stays within one cell of x on
+// every axis, so only triangles whose bounding box, widened by one cell,
+// holds x can meet it.  Looking only at these gives the same nearest hit as
+// testing every triangle.
+struct MeshIndex {
+  std::unordered_map<int64_t, std::vector<int64_t>> near;
+  void build(const OrcParams& P) {
+    for (int64_t k = 0; k < P.ntris; ++k) {
+      const float* t = P.tris + 9 * k;
+      int lo[3], hi[3];
+      for (int a = 0; a < 3; ++a) {
+        const double mn = std::min({double(t[a]), double(t[3 + a]), double(t[6 + a])});
+        const double mx = std::max({double(t[a]), double(t[3 + a]), double(t[6 + a])});
+        lo[a] = int(std::floor(mn)) - 1;
+        hi[a] = int(std::ceil(mx)) + 1;
+      }
+      for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+          for (int x = lo[0]; x <= hi[0]; ++x) {
+            if (x < 0 || y < 0 || z < 0 || x >= P.nx || y >= P.ny || z >= P.nz) continue;
+            near[int64_t(x) + int64_t(P.nx) * (int64_t(y) + int64_t(P.ny) * z)].push_back(k);
+          }
+    }
+  }
+};
+
 template <class T>
 struct Grid {
   const OrcParams& P;
   const uint8_t* mask;
   int64_t N;
-  Grid(const OrcParams& p, const uint8_t* m) : P(p), mask(m) { N = int64_t(p.nx) * p.ny * p.nz; }
+  MeshIndex mesh;
+  Grid(const OrcParams& p, const uint8_t* m) : P(p), mask(m) {
+    N = int64_t(p.nx) * p.ny * p.nz;
+    if (p.wall_rule == 2 && p.tris) mesh.build(p);
+  }
   int64_t idx(int x, int y, int z) const { return int64_t(x) + int64_t(P.nx) * (int64_t(y) + int64_t(P.ny) * z); }
   bool solid(int64_t c) const { return mask && mask[c]; }
 };
+
+// Where the segment from the origin to d meets triangle (v0, v1, v2) (all in
+// coordinates relative to the segment's start): the parameter t in [0, 1] of
+// the point t d, or -1 when it misses.  Points on an edge count as hits.
+// Moller & Trumbore, "Fast, minimum storage ray-triangle intersection",
+// J. Graphics Tools 2(1), 1997, restricted to the segment.
+double segment_triangle(const double d[3], const double v0[3], const double v1[3], const double v2[3]) {
+  const double tol = 1e-9;
+  double e1[3], e2[3];
+  for (int a = 0; a < 3; ++a) {
+    e1[a] = v1[a] - v0[a];
+    e2[a] = v2[a] - v0[a];
+  }
+  const double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+  const double det = e1[0] * p[0] + e1[1] * p[1] + e1[2] * p[2];
+  if (std::fabs(det) < 1e-300) return -1.0;  // segment parallel to the triangle's plane
+  const double inv = 1.0 / det;
+  const double s[3] = {-v0[0], -v0[1], -v0[2]};
+  const double u = (s[0] * p[0] + s[1] * p[1] + s[2] * p[2]) * inv;
+  if (u < -tol || u > 1.0 + tol) return -1.0;
+  const double q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
+  const double v = (d[0] * q[0] + d[1] * q[1] + d[2] * q[2]) * inv;
+  if (v < -tol || u + v > 1.0 + tol) return -1.0;
+  const double t = (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]) * inv;
+  if (t < -tol || t > 1.0 + tol) return -1.0;
+  return std::min(std::max(t, 0.0), 1.0);
+}
 
 template <class T>
 Cell<T> load_post(const OrcParams& P, const T* in, int64_t N, int64_t c) {
@@ -254,7 +328,7 @@ Cell<T> load_post(const OrcParams& P, const T* in, int64_t N, int64_t c) {
 
 // Velocity of object `id` at the midpoint p of the link from (x, y, z) along
 // -c (R16): V + W x (p - C).
-inline void wall_velocity(const OrcParams& P, int id, int x, int y, int z, int cx, int cy, int cz, double u[3]) {
+inline void wall_velocity_at(const OrcParams& P, int id, const double p[3], double u[3]) {
   double C[3] = {0, 0, 0}, V[3] = {0, 0, 0}, W[3] = {0, 0, 0};
   if (P.objects) {
     for (int a = 0; a < 3; ++a) {
@@ -263,10 +337,53 @@ inline void wall_velocity(const OrcParams& P, int id, int x, int y, int z, int c
       W[a] = P.objects[9 * id + 6 + a];
     }
   }
-  const double r[3] = {x - 0.5 * cx - C[0], y - 0.5 * cy - C[1], z - 0.5 * cz - C[2]};
+  const double r[3] = {p[0] - C[0], p[1] - C[1], p[2] - C[2]};
   u[0] = V[0] + W[1] * r[2] - W[2] * r[1];
   u[1] = V[1] + W[2] * r[0] - W[0] * r[2];
   u[2] = V[2] + W[0] * r[1] - W[1] * r[0];
+}
+
+inline void wall_velocity(const OrcParams& P, int id, int x, int y, int z, int cx, int cy, int cz, double u[3]) {
+  const double p[3] = {x - 0.5 * cx, y - 0.5 * cy, z - 0.5 * cz};
+  wall_velocity_at(P, id, p, u);
+}
+
+// The boundary point of the link from fluid cell (x, y, z) along -c to its
+// solid source s (R16, R26): wall rule 2 takes the nearest point where the
+// link meets a triangle (ties to the lowest triangle index) and that
+// triangle's object; a link that meets no triangle, and wall rule 1, take the
+// link midpoint and the object of s.  Returns whether a triangle was met.
+template <class T>
+bool link_boundary_point(const Grid<T>& G, int x, int y, int z, int cx, int cy, int cz, int64_t s, double p[3],
+                         int* id) {
+  const OrcParams& P = G.P;
+  p[0] = x - 0.5 * cx;
+  p[1] = y - 0.5 * cy;
+  p[2] = z - 0.5 * cz;
+  *id = G.mask[s];
+  if (P.wall_rule != 2) return false;
+  const auto it = G.mesh.near.find(G.idx(x, y, z));
+  if (it == G.mesh.near.end()) return false;
+  const double d[3] = {-double(cx), -double(cy), -double(cz)};
+  double best = 2.0;
+  int64_t bk = -1;
+  for (const int64_t k : it->second) {
+    const float* t = P.tris + 9 * k;
+    const double v0[3] = {t[0] - double(x), t[1] - double(y), t[2] - double(z)};
+    const double v1[3] = {t[3] - double(x), t[4] - double(y), t[5] - double(z)};
+    const double v2[3] = {t[6] - double(x), t[7] - double(y), t[8] - double(z)};
+    const double h = segment_triangle(d, v0, v1, v2);
+    if (h >= 0.0 && (h < best || (h == best && k < bk))) {
+      best = h;
+      bk = k;
+    }
+  }
+  if (bk < 0) return false;
+  p[0] = x - best * cx;
+  p[1] = y - best * cy;
+  p[2] = z - best * cz;
+  *id = P.tri_obj[bk];
+  return true;
 }
 
 // f_i arriving at fluid cell (x, y, z) after the pull-stream, with the face
@@ -297,10 +414,21 @@ T pulled(const Grid<T>& G, int x, int y, int z, int i, PostFn&& post) {
   const int64_t s = G.idx(sx, sy, sz);
   if (G.solid(s)) {
     if (P.wall_rule == 0) return hermite_f(LAT.opp[i], post(G.idx(x, y, z)), lit);
-    // moment wall (R16): rho^p = rho^x, u^p of the object, S^p = u^p u^p + (S^x - u^x u^x)
+    // moment wall (R16, R26): rho^p = rho^x, u^p of the object at p, S^p = u^p u^p + (S^x - u^x u^x)
     const Cell<T> q = post(G.idx(x, y, z));
-    double up[3];
-    wall_velocity(P, G.mask[s], x, y, z, cx, cy, cz, up);
+    double pp[3], up[3];
+    int id = 0;
+    if (!link_boundary_point(G, x, y, z, cx, cy, cz, s, pp, &id) && P.wall_rule == 2) {
+      // a link that meets no triangle is not coupled: the pull from the resting solid cell
+      Cell<T> rest;
+      rest.rho = T(1.0);
+      for (int a = 0; a < 3; ++a) {
+        rest.u[a] = T(0.0);
+        for (int b = 0; b < 3; ++b) rest.S[a][b] = T(0.0);
+      }
+      return hermite_f(i, rest, lit);
+    }
+    wall_velocity_at(P, id, pp, up);
     Cell<T> pc;
     pc.rho = q.rho;
     for (int a = 0; a < 3; ++a) pc.u[a] = T(up[a]);
@@ -667,7 +795,9 @@ int orc_object_forces(const OrcParams* P, const uint8_t* mask, const double* in,
           if (!P->inflow) sx = wrap(sx, P->nx);
           const int64_t s = G.idx(sx, wrap(y - cy, P->ny), wrap(z - cz, P->nz));
           if (!G.solid(s)) continue;
-          const int id = mask[s];
+          double pp[3];
+          int id = 0;
+          link_boundary_point(G, x, y, z, cx, cy, cz, s, pp, &id);
           const double f_in = pulled(G, x, y, z, i, get);
           const double f_out = hermite_f(LAT.opp[i], get(c), P->literal_xyz != 0);
           double dp[3];
@@ -675,7 +805,7 @@ int orc_object_forces(const OrcParams* P, const uint8_t* mask, const double* in,
           double C[3] = {0, 0, 0};
           if (P->objects)
             for (int a = 0; a < 3; ++a) C[a] = P->objects[9 * id + a];
-          const double r[3] = {x - 0.5 * cx - C[0], y - 0.5 * cy - C[1], z - 0.5 * cz - C[2]};
+          const double r[3] = {pp[0] - C[0], pp[1] - C[1], pp[2] - C[2]};
           double* o = out + 6 * id;
           for (int a = 0; a < 3; ++a) o[a] += dp[a];
           o[3] += r[1] * dp[2] - r[2] * dp[1];
@@ -684,6 +814,45 @@ int orc_object_forces(const OrcParams* P, const uint8_t* mask, const double* in,
         }
       }
   return 0;
+}
+
+// The boundary points of wall rule 2 (R26): for every link from a fluid cell
+// to a solid source (with the x faces open, not the face links), writes
+// (cell, i, met a triangle, p_x, p_y, p_z, object id) into out (7 doubles per
+// link, up to cap links); returns the number of links.
+int64_t orc_mesh_links(const OrcParams* P, const uint8_t* mask, double* out, int64_t cap) {
+  Grid<double> G(*P, mask);
+  int64_t n = 0;
+  if (!mask) return 0;
+  for (int z = 0; z < P->nz; ++z)
+    for (int y = 0; y < P->ny; ++y)
+      for (int x = 0; x < P->nx; ++x) {
+        const int64_t c = G.idx(x, y, z);
+        if (G.solid(c)) continue;
+        for (int i = 0; i < 27; ++i) {
+          const int cx = LAT.c[i][0], cy = LAT.c[i][1], cz = LAT.c[i][2];
+          if (P->inflow && ((x == 0 && cx == +1) || (x == P->nx - 1 && cx == -1))) continue;
+          int sx = x - cx;
+          if (!P->inflow) sx = wrap(sx, P->nx);
+          const int64_t s = G.idx(sx, wrap(y - cy, P->ny), wrap(z - cz, P->nz));
+          if (!G.solid(s)) continue;
+          double pp[3];
+          int id = 0;
+          const bool met = link_boundary_point(G, x, y, z, cx, cy, cz, s, pp, &id);
+          if (n < cap) {
+            double* o = out + 7 * n;
+            o[0] = double(c);
+            o[1] = i;
+            o[2] = met ? 1.0 : 0.0;
+            o[3] = pp[0];
+            o[4] = pp[1];
+            o[5] = pp[2];
+            o[6] = id;
+          }
+          ++n;
+        }
+      }
+  return n;
 }
 
 int orc_step_f32(const OrcParams* P, const uint8_t* mask, const float* in, float* out, int nthreads) {
@@ -849,13 +1018,13 @@ int orc_q16_step_cells(const OrcParams* P, const uint8_t* mask, const uint32_t* 
 // lam_prev = J(m_t)^T lam_next for one FP64 step (fields of 10 planes).
 int orc_adjoint_step(const OrcParams* P, const uint8_t* mask, const double* m_t, const double* lam_next,
                      double* lam_prev, int nthreads) {
-  (void)nthreads;
   if (P->wall_rule != 0) return -1;  // the adjoint follows bounce-back walls only
   Grid<double> G(*P, mask);
   const int64_t N = G.N;
   const bool lit = P->literal_xyz != 0;
-  // Jf[c][i][k] = d f+_i(c) / d m_k(c)
+  // Jf[c][i][k] = d f+_i(c) / d m_k(c), one cell at a time (cells in parallel)
   std::vector<double> Jf(size_t(N) * 270, 0.0);
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
   for (int64_t c = 0; c < N; ++c) {
     if (G.solid(c)) continue;
     for (int k = 0; k < 10; ++k) {
@@ -927,7 +1096,6 @@ int orc_adjoint_step(const OrcParams* P, const uint8_t* mask, const double* m_t,
 // Solid cells get zeros.  out: ncells x 10.
 int orc_adjoint_step_cells(const OrcParams* P, const uint8_t* mask, const double* m_t, const double* lam_next,
                            int64_t ncells, const int64_t* cells, double* out, int nthreads) {
-  (void)nthreads;
   if (P->wall_rule != 0) return -1;
   Grid<double> G(*P, mask);
   const int64_t N = G.N;
@@ -945,6 +1113,7 @@ int orc_adjoint_step_cells(const OrcParams* P, const uint8_t* mask, const double
     for (int k = 0; k < 10; ++k) lf += phi[k] * lam_next[k * N + c];
     return lf;
   };
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
   for (int64_t n = 0; n < ncells; ++n) {
     const int64_t s = cells[n];
     double* o = out + 10 * n;

@@ -146,12 +146,9 @@ def _objects_mask(shape, kinds, centres, sizes, scale, periodic):
     return mask
 
 
-def channel_mask(nx=1000, ny=400, nz=400, count=300, target=0.06, seed=0, tol=0.003):
-    """Solid mask (nz, ny, nx) uint8 of the obstacle channel.  The scale s is
-    bisected on a 4x coarser grid so that the union's solid fraction is
-    target +- tol, then the mask is drawn at full resolution.  Cells within 2
-    of the x faces stay fluid."""
-    kinds, centres, sizes = channel_obstacles(nx, ny, nz, count, target, seed)
+def _channel_scale(nx, ny, nz, kinds, centres, sizes, target, tol=0.003):
+    """The obstacle scale s: bisected on a 4x coarser grid until the union's
+    solid fraction is target +- tol/4."""
     c = 4
     shape_c = (max(1, nz // c), max(1, ny // c), max(1, nx // c))
     lo, hi = 0.05, 4.0
@@ -165,6 +162,16 @@ def channel_mask(nx=1000, ny=400, nz=400, count=300, target=0.06, seed=0, tol=0.
             lo = s
         else:
             hi = s
+    return s
+
+
+def channel_mask(nx=1000, ny=400, nz=400, count=300, target=0.06, seed=0, tol=0.003):
+    """Solid mask (nz, ny, nx) uint8 of the obstacle channel.  The scale s is
+    bisected on a 4x coarser grid so that the union's solid fraction is
+    target +- tol, then the mask is drawn at full resolution.  Cells within 2
+    of the x faces stay fluid."""
+    kinds, centres, sizes = channel_obstacles(nx, ny, nz, count, target, seed)
+    s = _channel_scale(nx, ny, nz, kinds, centres, sizes, target, tol)
     mask = _objects_mask((nz, ny, nx), kinds, centres, sizes, s, False)
     mask[:, :, :3] = 0
     mask[:, :, nx - 3:] = 0
@@ -211,3 +218,159 @@ def batched_domain_fields(dom):
     mask = sphere_mask(nx, ny, nz, dom["phi"], 3.0, rmax, seed=dom["seed"])
     u = random_solenoidal(nx, ny, nz, 4.0, 0.05, seed=dom["seed"] + 1)
     return mask, u
+
+
+# ------------------------------------------------------------------ meshes ---
+# Triangle meshes of the channel's obstacles, for the per-triangle solid
+# correction.  Every obstacle is a closed convex polyhedron: an axis-aligned
+# box whose faces are cut into small triangles, or a latitude-longitude
+# polyhedron inscribed in an axis-aligned ellipsoid.  The solid mask of a mesh
+# scene marks the lattice points inside a polyhedron (on its surface counts as
+# inside), so every link from a fluid cell to a solid one crosses a mesh.
+
+def _sphere_grid(nt: int, nph: int):
+    """Unit-sphere vertices V[k, l] (k = 0..nt polar, l = 0..nph azimuthal,
+    column nph repeating column 0)."""
+    th = np.pi * np.arange(nt + 1) / nt
+    ph = 2.0 * np.pi * (np.arange(nph + 1) % nph) / nph
+    st, ct = np.sin(th)[:, None], np.cos(th)[:, None]
+    return np.stack([st * np.cos(ph)[None, :], st * np.sin(ph)[None, :], np.broadcast_to(ct, (nt + 1, nph + 1))], -1)
+
+
+def _sphere_facets(nt: int, nph: int):
+    """Triangles (T, 3, 3) of the unit polyhedron with nt bands and nph
+    sectors, and its facet planes n.x <= d per (band, sector): n (nt, nph, 3),
+    d (nt, nph).  Band quads are planar (two triangles, one plane); the polar
+    bands are fans of single triangles."""
+    V = _sphere_grid(nt, nph)
+    k = np.arange(nt)[:, None]
+    l = np.arange(nph)[None, :]
+    v00, v01, v10, v11 = V[k, l], V[k, l + 1], V[k + 1, l], V[k + 1, l + 1]
+    # plane of each facet from three of its distinct corners
+    a = np.where((k == 0)[..., None], v00, v00)
+    b = np.where((k == nt - 1)[..., None], v10, v10)
+    c = np.where((k == nt - 1)[..., None], v01, v11)
+    n = np.cross(b - a, c - a)
+    n = n / np.linalg.norm(n, axis=-1, keepdims=True)
+    d = (n * a).sum(-1)
+    flip = d < 0
+    n[flip] *= -1.0
+    d[flip] *= -1.0
+    tris = []
+    tris.append(np.stack([v00[0], v10[0], v11[0]], 1))                 # north fan
+    if nt > 2:
+        mid = slice(1, nt - 1)
+        tris.append(np.stack([v00[mid], v10[mid], v11[mid]], 2).reshape(-1, 3, 3))
+        tris.append(np.stack([v00[mid], v11[mid], v01[mid]], 2).reshape(-1, 3, 3))
+    tris.append(np.stack([v00[nt - 1], v10[nt - 1], v01[nt - 1]], 1))  # south fan
+    return np.concatenate(tris, 0), n, d
+
+
+def ellipsoid_mesh(center, semi, edge: float = 1.5):
+    """Mesh of the polyhedron inscribed in an axis-aligned ellipsoid, with
+    edges of about `edge` cells: (triangles (T, 3, 3), (nt, nph))."""
+    a = np.asarray(semi, float)
+    nt = max(4, int(np.ceil(np.pi * a.max() / edge)))
+    nph = max(8, int(np.ceil(2.0 * np.pi * a.max() / edge)))
+    unit, _, _ = _sphere_facets(nt, nph)
+    return np.asarray(center, float) + unit * a, (nt, nph)
+
+
+def inside_ellipsoid_mesh(points, center, semi, grid):
+    """Whether points (..., 3) lie inside (or on) the inscribed polyhedron of
+    ellipsoid_mesh: in the frame where the ellipsoid is the unit sphere, the
+    facets near the point's direction (one band and sector either side of
+    the one it points into) must all hold it."""
+    nt, nph = grid
+    _, n, d = _sphere_facets(nt, nph)
+    q = (np.asarray(points, float) - np.asarray(center, float)) / np.asarray(semi, float)
+    r = np.linalg.norm(q, axis=-1)
+    th = np.arccos(np.clip(q[..., 2] / np.maximum(r, 1e-300), -1.0, 1.0))
+    ph = np.mod(np.arctan2(q[..., 1], q[..., 0]), 2.0 * np.pi)
+    k0 = np.clip((th / (np.pi / nt)).astype(int), 0, nt - 1)
+    l0 = np.clip((ph / (2.0 * np.pi / nph)).astype(int), 0, nph - 1)
+    inside = r <= 1.0
+    for dk in (-1, 0, 1):
+        kk = np.clip(k0 + dk, 0, nt - 1)
+        for dl in (-1, 0, 1):
+            ll = np.mod(l0 + dl, nph)
+            inside &= (n[kk, ll] * q).sum(-1) <= d[kk, ll]
+    return inside
+
+
+def box_mesh(center, half, edge: float = 1.5):
+    """Mesh of an axis-aligned box (center, half-extents): every face cut
+    into a grid of quads of about `edge` cells, two triangles each."""
+    c = np.asarray(center, float)
+    h = np.asarray(half, float)
+    tris = []
+    for ax in range(3):
+        u, v = [a for a in range(3) if a != ax]
+        nu = max(1, int(np.ceil(2.0 * h[u] / edge)))
+        nv = max(1, int(np.ceil(2.0 * h[v] / edge)))
+        su = -h[u] + 2.0 * h[u] * np.arange(nu + 1) / nu
+        sv = -h[v] + 2.0 * h[v] * np.arange(nv + 1) / nv
+        for sgn in (-1.0, 1.0):
+            P = np.zeros((nu + 1, nv + 1, 3))
+            P[..., ax] = sgn * h[ax]
+            P[..., u] = su[:, None]
+            P[..., v] = sv[None, :]
+            p00, p10, p01, p11 = P[:-1, :-1], P[1:, :-1], P[:-1, 1:], P[1:, 1:]
+            tris.append(np.stack([p00, p10, p11], 2).reshape(-1, 3, 3))
+            tris.append(np.stack([p00, p11, p01], 2).reshape(-1, 3, 3))
+    return c + np.concatenate(tris, 0)
+
+
+def mesh_scene(shape, objects, edge: float = 1.5):
+    """Solid mask and triangle list of closed convex obstacles.  objects:
+    (kind, center (x, y, z), size (3), id) with kind 0 an ellipsoid
+    (semi-axes) and kind 1 a box (half-extents), id in 1..255 (the mask value
+    of its cells and the object of its triangles).  Returns (mask (nz, ny, nx)
+    uint8, triangles (T, 9) float32 as x0 y0 z0 x1 ... z2, object id per
+    triangle (T,) uint8).  The mask marks the lattice points inside a
+    polyhedron of the exact geometry; the triangles are its vertices rounded
+    to float32, so a lattice point within rounding distance (about 1e-7 of
+    its coordinates) of a facet may lie on the other side of the rounded
+    mesh."""
+    nz, ny, nx = shape
+    mask = np.zeros(shape, dtype=np.uint8)
+    tris, ids = [], []
+    for kind, c, size, oid in objects:
+        c = np.asarray(c, float)
+        size = np.asarray(size, float)
+        if kind == 0:
+            t, grid = ellipsoid_mesh(c, size, edge)
+        else:
+            t = box_mesh(c, size, edge)
+        lo = np.maximum(np.floor(c - size).astype(int) - 1, 0)
+        hi = np.minimum(np.ceil(c + size).astype(int) + 2, [nx, ny, nz])
+        if np.any(hi <= lo):
+            continue
+        Z, Y, X = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]), np.arange(lo[0], hi[0]),
+                              indexing="ij")
+        pts = np.stack([X, Y, Z], -1).astype(float)
+        if kind == 0:
+            ins = inside_ellipsoid_mesh(pts, c, size, grid)
+        else:
+            ins = np.all(np.abs(pts - c) <= size, axis=-1)
+        sub = mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        sub[ins] = np.uint8(oid)
+        tris.append(t.reshape(-1, 9))
+        ids.append(np.full(t.shape[0], oid, np.uint8))
+    if not tris:
+        return mask, np.zeros((0, 9), np.float32), np.zeros(0, np.uint8)
+    return mask, np.concatenate(tris).astype(np.float32), np.concatenate(ids)
+
+
+def channel_mesh(nx=1000, ny=400, nz=400, count=300, target=0.06, seed=0, edge=1.5):
+    """The obstacle channel of channel_mask with its ellipsoids and boxes as
+    triangle meshes (object id 1 for all): (mask, triangles, ids).  The
+    ellipsoids' polyhedra are inscribed, so the solid fraction is a little
+    below channel_mask's."""
+    kinds, centres, sizes = channel_obstacles(nx, ny, nz, count, target, seed)
+    s = _channel_scale(nx, ny, nz, kinds, centres, sizes, target)
+    objs = [(int(k), c, np.maximum(h * s, 0.5), 1) for k, c, h in zip(kinds, centres, sizes)]
+    mask, tris, ids = mesh_scene((nz, ny, nx), objs, edge)
+    mask[:, :, :3] = 0
+    mask[:, :, nx - 3:] = 0
+    return mask, tris, ids
