@@ -106,7 +106,12 @@ typedef struct lbm_options {
                          S^p = u^p u^p + (S^x - u^x u^x) of x's post-collision moments.
                          The reconstruction does not depend on where p lies on the link,
                          so the no-slip point of a voxel wall is the solid node.  Not
-                         supported by lbm_adjoint_step nor by batches. */
+                         supported by lbm_adjoint_step nor by batches.
+                         2 (mixed pipeline only, else LBM_ERR_UNSUPPORTED): the same
+                         coupling with p where the link first meets the obstacle meshes
+                         of lbm_set_triangles and u^p from that triangle's object,
+                         applied by the per-triangle solid correction of Sec. 4.2
+                         (Alg. 3) instead of per-link corrections. */
   int track_forces;   /* 1: every step adds the force and torque the fluid exerts on each
                          object (momentum exchange over its links, -(f_i(x) + f+_opp(i)(x)) c_i
                          per link, torque about the object's center) to sums read by
@@ -125,6 +130,12 @@ typedef struct lbm_options {
                          are not supported.  lbm_get_moments returns the post-stream
                          moments, as in pipeline 0.  Switching moves the current moments to
                          the other storage. */
+  int graph_steps;    /* 256 (default), 1..4096: lbm_step (pipeline 0) replays captured HIP
+                         graphs of up to this many steps, each step's dither key read from a
+                         device-side step counter set before the replay, so the result is
+                         the same as launching every kernel (graphs are captured on first
+                         use and dropped when options or the boundary list change); 0:
+                         every kernel is launched one by one. */
 } lbm_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -181,6 +192,18 @@ int lbm_set_equilibrium(lbm_ctx* ctx, const float* rho, const float* u, int on_d
  * lbm_set_step_count) is drawn from (cell, t, seed).
  */
 int lbm_step(lbm_ctx* ctx, int n);
+
+/*
+ * Does ahead of time, without advancing the state, what the first
+ * lbm_step(ctx, n) would do before its first kernel: builds the boundary list
+ * if needed and, with graph_steps > 0 and pipeline 0, captures and
+ * instantiates the step sequences that lbm_step(ctx, n) replays, from either
+ * buffer, so that a later lbm_step(ctx, n) only launches them.  Synchronous;
+ * the captures are dropped like any others (options or boundary list
+ * changed, or more than eight sequences held).  Errors: LBM_ERR_INVALID_ARG
+ * for a NULL ctx or n < 0, LBM_ERR_HIP from the capture.
+ */
+int lbm_prepare(lbm_ctx* ctx, int n);
 
 /* Writes the current state as a full moment field (ten planes); solid cells read as rest. */
 int lbm_get_moments(lbm_ctx* ctx, float* m, int on_device);
@@ -291,6 +314,26 @@ int lbm_adjoint_step_noalloc(lbm_ctx* ctx, const float* m_t, const float* lam_ne
  */
 int lbm_equilibrium_vjp(lbm_ctx* ctx, const float* rho, const float* u, const float* lam, float* grad_rho,
                         float* grad_u);
+
+/*
+ * Obstacle meshes for wall rule 2 (Sec. 4.2, Alg. 3): ntris triangles, tris
+ * a host array of 9 floats per triangle (x0 y0 z0 x1 y1 z1 x2 y2 z2, lattice
+ * units, cell (x, y, z) at integer coordinates, not wrapped), obj a host
+ * array of ntris object ids (1..255, the lbm_set_object ids that give each
+ * triangle's wall motion).  Both are copied; ntris = 0 removes the meshes.
+ * The solid mask still decides which links are replaced: every link from a
+ * fluid cell to a solid one should meet a triangle (the mask should mark the
+ * lattice points inside the closed meshes); a link that meets none keeps the
+ * distribution the stream pass pulled from the solid cell.  One thread per
+ * triangle visits the listed fluid cells of its bounding box (widened by one
+ * cell) and tests their links to solid sources; the nearest hit on a link
+ * (ties to the lowest triangle index) is found once per mesh and boundary
+ * list, and each step the winning triangle adds (f_i(p) - f_i pulled) times
+ * the link's moments to the cell's FP32 post-stream moments with atomicAdd.
+ * Synchronises.  Errors: LBM_ERR_INVALID_ARG (NULL arrays, non-finite
+ * vertices), LBM_ERR_OUT_OF_MEMORY, LBM_ERR_DEVICE.
+ */
+int lbm_set_triangles(lbm_ctx* ctx, int64_t ntris, const float* tris, const uint8_t* obj);
 
 /* Waits for all work on the context stream. */
 int lbm_synchronize(lbm_ctx* ctx);

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <iterator>
 #include <cstdio>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <cstring>
 #include <new>
 #include <string>
@@ -50,10 +52,21 @@ struct lbm_ctx {
   uint32_t* d_links = nullptr;        // changed links, 32 e + i
   int64_t n_links = 0;
   bool links_built = false;
+  // obstacle meshes of wall rule 2 (per-triangle solid correction)
+  float* d_tris = nullptr;
+  uint8_t* d_tri_obj = nullptr;
+  int64_t n_tris = 0;
+  unsigned long long* d_winner = nullptr;  // nearest-hit key per listed fluid entry and link
+  bool winners_built = false;
   bool flags_valid = false;
   bool list_built = false;
   int list_inflow = -1;
   uint64_t t = 0;
+  // captured step sequences (graph_steps > 0): the dither key of each step
+  // comes from the device-side counter d_step, set before every replay
+  uint32_t* d_step = nullptr;
+  hipStream_t cap = nullptr;                              // capture stream
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (steps, first buffer) -> sequence
   std::string err;
 };
 
@@ -84,7 +97,13 @@ void planes_of(const lbm_ctx* c, void* base, void* out[10]) {
 
 Geometry geom(const lbm_ctx* c) { return Geometry{c->nx, c->ny, c->nz, c->opt.inflow}; }
 
+void drop_graphs(lbm_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
 void free_list(lbm_ctx* c) {
+  drop_graphs(c);  // they hold the list's pointers
   if (c->d_cells) (void)hipFree(c->d_cells);
   if (c->d_bits) (void)hipFree(c->d_bits);
   if (c->d_yz) (void)hipFree(c->d_yz);
@@ -101,6 +120,10 @@ void free_list(lbm_ctx* c) {
   c->n_fluid_b = c->n_solid_b = c->n_fluid_run = 0;
   c->list_built = false;
   c->flags_valid = false;
+  c->links_built = false;
+  c->winners_built = false;
+  if (c->d_winner) (void)hipFree(c->d_winner);
+  c->d_winner = nullptr;
 }
 
 // Builds the boundary list on the device: count pass (counts and the bitmap
@@ -226,26 +249,30 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   return p;
 }
 
-// One step from in to out: fluid pass then boundary pass.
-int enqueue_pass(lbm_ctx* c, const void* in, void* out, hipEvent_t ev[4]) {
-  const StepParams p = step_params(c, in, out);
+// The kernels of one step on stream s: fluid pass then boundary pass.
+int launch_pass(lbm_ctx* c, const StepParams& p, hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipSuccess;
-  if (ev) e = hipEventRecord(ev[0], c->stream);
-  if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->opt.tile_rows, c->stream);
-  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], c->stream);
+  if (ev) e = hipEventRecord(ev[0], s);
+  if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->opt.tile_rows, s);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
   if (e != hipSuccess) return hip_fail(c, e, "fluid pass");
   const int64_t n = c->n_fluid_b + c->n_solid_b;
   if (n > 0) {
-    if (ev) e = hipEventRecord(ev[2], c->stream);
+    if (ev) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess)
-      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_run), 0,
-                          c->stream);
+      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_run), 0, s);
     if (e == hipSuccess && c->n_solid_b > 0)
-      e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b),
-                          c->stream);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
+      e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b), s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
+  return LBM_OK;
+}
+
+// One step from in to out: fluid pass then boundary pass.
+int enqueue_pass(lbm_ctx* c, const void* in, void* out, hipEvent_t ev[4]) {
+  const int r = launch_pass(c, step_params(c, in, out), c->stream, ev);
+  if (r != LBM_OK) return r;
   c->t += 1;
   return LBM_OK;
 }
@@ -255,6 +282,52 @@ int enqueue_step(lbm_ctx* c, hipEvent_t ev[4]) {
   const int r = enqueue_pass(c, c->buf[c->cur], c->buf[1 - c->cur], ev);
   if (r == LBM_OK) c->cur = 1 - c->cur;
   return r;
+}
+
+// The captured sequence of k steps starting from buffer `first`: step j reads
+// buf[(first + j) & 1], writes the other, and takes its dither key from the
+// device counter plus j.
+int graph_for(lbm_ctx* c, int k, int first, hipGraphExec_t* out) {
+  const auto key = std::make_pair(k, first);
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return LBM_OK;
+  }
+  if (c->graphs.size() >= 8) drop_graphs(c);
+  hipError_t e = hipSuccess;
+  if (!c->cap) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreate (capture)");
+  e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+  int r = LBM_OK;
+  for (int j = 0; j < k && r == LBM_OK; ++j) {
+    StepParams p = step_params(c, c->buf[(first + j) & 1], c->buf[(first + j + 1) & 1]);
+    p.step_ctr = c->d_step;
+    p.step_off = uint32_t(j);
+    p.seed = c->opt.seed;
+    p.dither_mode = c->fmt != FMT_F32 ? c->opt.dither_mode : 0;
+    r = launch_pass(c, p, c->cap, nullptr);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (r != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+  e = hipGraphUpload(x, c->stream);  // ahead of the first launch
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(x);
+    return hip_fail(c, e, "hipGraphUpload");
+  }
+  c->graphs[key] = x;
+  *out = x;
+  return LBM_OK;
 }
 
 // ---- the mixed pipeline
@@ -274,7 +347,7 @@ int build_links(lbm_ctx* c) {
       const int cx = (b & BIT_INFLOW) ? 1 : -1;
       for (int cz = -1; cz <= 1; ++cz)
         for (int cy = -1; cy <= 1; ++cy) links.push_back(uint32_t(k) * 32u + uint32_t((cx + 1) + 3 * (cy + 1) + 9 * (cz + 1)));
-    } else {
+    } else if (c->opt.wall_rule != 2) {  // wall rule 2: the triangles correct the solid links
       for (uint32_t i = 0; i < 27; ++i)
         if (i != 13 && ((b >> i) & 1u)) links.push_back(uint32_t(k) * 32u + i);
     }
@@ -309,10 +382,31 @@ int mixed_requantize(lbm_ctx* c, bool dither, hipEvent_t ev0, hipEvent_t ev1) {
   return LBM_OK;
 }
 
+// Nearest-hit keys of wall rule 2's links (static geometry: built once per
+// boundary list and triangle set).
+int build_winners(lbm_ctx* c) {
+  if (!c->d_tris || c->n_tris <= 0) return fail(c, LBM_ERR_INVALID_ARG, "wall_rule 2 needs lbm_set_triangles");
+  hipError_t e = hipSuccess;
+  if (!c->d_winner && c->n_fluid_b > 0) e = hipMalloc(&c->d_winner, size_t(c->n_fluid_b) * 27 * 8);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMalloc(triangle winners)");
+  if (c->n_fluid_b > 0) {
+    const StepParams p = step_params(c, c->buf[c->cur], c->buf[c->cur]);
+    const TriangleSet T{c->d_tris, c->d_tri_obj, int(c->n_tris), c->d_lpack, c->d_bits};
+    e = launch_triangle_winners(p, T, c->d_winner, c->n_fluid_b, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "triangle winners");
+  }
+  c->winners_built = true;
+  return LBM_OK;
+}
+
 // One step of the mixed pipeline: stream pass, link corrections, requantize.
 int enqueue_mixed_step(lbm_ctx* c, hipEvent_t ev[6]) {
   if (!c->links_built) {
     const int r = build_links(c);
+    if (r != LBM_OK) return r;
+  }
+  if (c->opt.wall_rule == 2 && !c->winners_built) {
+    const int r = build_winners(c);
     if (r != LBM_OK) return r;
   }
   StepParams p = step_params(c, c->buf[c->cur], c->buf[c->cur]);
@@ -327,6 +421,12 @@ int enqueue_mixed_step(lbm_ctx* c, hipEvent_t ev[6]) {
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], c->stream);
   if (e == hipSuccess)
     e = launch_mixed_links(p, c->d_links, int(c->n_links), c->d_cells, c->d_yz, c->d_bits, c->stream);
+  if (e == hipSuccess && c->opt.wall_rule == 2) {
+    // the stream pass keeps no side records (p.lc is empty); the triangles
+    // find listed cells through the list's own bitmap
+    const TriangleSet T{c->d_tris, c->d_tri_obj, int(c->n_tris), c->d_lpack, c->d_bits};
+    e = launch_triangle_correction(p, T, c->d_winner, c->stream);
+  }
   if (e == hipSuccess && ev) e = hipEventRecord(ev[3], c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "mixed stream pass");
   const int r = mixed_requantize(c, true, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr);
@@ -390,6 +490,7 @@ int lbm_default_options(lbm_options* o) {
   o->seed = 0;
   o->inflow = 0;
   o->check_health = 1;
+  o->graph_steps = 256;
   return LBM_OK;
 }
 
@@ -426,6 +527,7 @@ int lbm_create(const int dims[3], double tau, const uint8_t* mask, int fmt, lbm_
   hipError_t e = hipSuccess;
   for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMalloc(&c->buf[b], state_bytes(c));
   if (e == hipSuccess) e = hipMalloc(&c->d_counters, 4 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&c->d_step, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&c->d_objects, sizeof(c->h_objects));
   if (e == hipSuccess) e = hipMemcpy(c->d_objects, c->h_objects, sizeof(c->h_objects), hipMemcpyHostToDevice);
@@ -474,11 +576,16 @@ int lbm_destroy(lbm_ctx* c) {
   if (c->d_mask) (void)hipFree(c->d_mask);
   free_list(c);
   if (c->d_counters) (void)hipFree(c->d_counters);
+  if (c->d_step) (void)hipFree(c->d_step);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->d_bad) (void)hipFree(c->d_bad);
   if (c->d_flags) (void)hipFree(c->d_flags);
   if (c->d_objects) (void)hipFree(c->d_objects);
   if (c->d_forces) (void)hipFree(c->d_forces);
   if (c->d_ps) (void)hipFree(c->d_ps);
+  if (c->d_tris) (void)hipFree(c->d_tris);
+  if (c->d_tri_obj) (void)hipFree(c->d_tri_obj);
+  if (c->d_winner) (void)hipFree(c->d_winner);
   if (c->d_links) (void)hipFree(c->d_links);
   delete c;
   return LBM_OK;
@@ -499,12 +606,16 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(o->force[a]) || std::fabs(o->force[a]) > 0.01f)
       return fail(c, LBM_ERR_INVALID_ARG, "force must be finite with |F_a| <= 0.01");
-  if (o->wall_rule != 0 && o->wall_rule != 1) return fail(c, LBM_ERR_INVALID_ARG, "wall_rule must be 0 or 1");
+  if (o->wall_rule < 0 || o->wall_rule > 2) return fail(c, LBM_ERR_INVALID_ARG, "wall_rule must be 0, 1 or 2");
+  if (o->wall_rule == 2 && o->pipeline != 1)
+    return fail(c, LBM_ERR_UNSUPPORTED, "wall_rule 2 (per-triangle solid correction) runs in the mixed pipeline");
   if (o->pipeline != 0 && o->pipeline != 1) return fail(c, LBM_ERR_INVALID_ARG, "pipeline must be 0 or 1");
   if (o->pipeline == 1 && (c->fmt != FMT_Q16 || o->force[0] != 0.0f || o->force[1] != 0.0f ||
                            o->force[2] != 0.0f || o->track_forces != 0))
     return fail(c, LBM_ERR_UNSUPPORTED, "the mixed pipeline runs 16-bit contexts without body force or force tracking");
   if (o->track_forces != 0 && o->track_forces != 1) return fail(c, LBM_ERR_INVALID_ARG, "track_forces must be 0 or 1");
+  if (o->graph_steps < 0 || o->graph_steps > 4096)
+    return fail(c, LBM_ERR_INVALID_ARG, "graph_steps must be in [0, 4096]");
   int r = check_faces(c, *o);
   if (r != LBM_OK) return r;
   if (o->inflow && c->d_mask) {
@@ -520,6 +631,8 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
     }
   }
   const int old_inflow = c->opt.inflow, old_pipeline = c->opt.pipeline;
+  drop_graphs(c);  // captured steps hold the old options
+  if (o->wall_rule != c->opt.wall_rule) c->links_built = false;  // wall rule 2 keeps only the face links
   c->opt = *o;
   c->opt.pipeline = old_pipeline;
   if (!c->list_built || old_inflow != o->inflow) {
@@ -604,9 +717,26 @@ int lbm_step(lbm_ctx* c, int n) {
     const int r = build_list(c);
     if (r != LBM_OK) return r;
   }
-  for (int s = 0; s < n; ++s) {
+  const bool graphs = c->opt.graph_steps > 0 && c->opt.pipeline != 1;
+  int left = n;
+  while (left > 0) {
+    if (graphs && left >= 2) {
+      // a replay of up to graph_steps captured steps, keys from the counter set here
+      const int k = std::min(left, c->opt.graph_steps);
+      hipGraphExec_t x = nullptr;
+      int r = graph_for(c, k, c->cur, &x);
+      if (r != LBM_OK) return r;
+      hipError_t e = launch_set_counter(c->d_step, uint32_t(c->t), c->stream);
+      if (e == hipSuccess) e = hipGraphLaunch(x, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+      c->cur = (c->cur + k) & 1;
+      c->t += uint64_t(k);
+      left -= k;
+      continue;
+    }
     const int r = c->opt.pipeline == 1 ? enqueue_mixed_step(c, nullptr) : enqueue_step(c, nullptr);
     if (r != LBM_OK) return r;
+    --left;
   }
   if (c->opt.check_health && n > 0) {
     uint64_t bad = 0;
@@ -638,6 +768,53 @@ int lbm_set_object(lbm_ctx* c, int id, const float center[3], const float veloci
   } else {
     return hip_fail(c, e, "set_object");
   }
+  return LBM_OK;
+}
+
+int lbm_prepare(lbm_ctx* c, int n) {
+  if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 0) return fail(c, LBM_ERR_INVALID_ARG, "n must be >= 0");
+  if (!c->list_built) {
+    const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  const int G = c->opt.graph_steps;
+  if (G <= 0 || c->opt.pipeline == 1) return LBM_OK;
+  // lbm_step(n) replays sequences of min(n, G) steps and, past G, one of the
+  // remainder (a single step is launched directly), from either buffer
+  const int sizes[2] = {std::min(n, G), n > G ? n % G : 0};
+  for (const int k : sizes) {
+    if (k < 2) continue;
+    for (int first = 0; first < 2; ++first) {
+      hipGraphExec_t x = nullptr;
+      const int r = graph_for(c, k, first, &x);
+      if (r != LBM_OK) return r;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_set_triangles(lbm_ctx* c, int64_t ntris, const float* tris, const uint8_t* obj) {
+  if (!c) return fail(nullptr, LBM_ERR_INVALID_ARG, "ctx is NULL");
+  if (ntris < 0 || ntris > (int64_t(1) << 31) - 1 || (ntris > 0 && (!tris || !obj)))
+    return fail(c, LBM_ERR_INVALID_ARG, "bad triangle list");
+  for (int64_t k = 0; k < 9 * ntris; ++k)
+    if (!std::isfinite(tris[k])) return fail(c, LBM_ERR_INVALID_ARG, "triangle vertices must be finite");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (c->d_tris) (void)hipFree(c->d_tris);
+  if (c->d_tri_obj) (void)hipFree(c->d_tri_obj);
+  c->d_tris = nullptr;
+  c->d_tri_obj = nullptr;
+  c->n_tris = 0;
+  c->winners_built = false;
+  if (e == hipSuccess && ntris > 0) {
+    e = hipMalloc(&c->d_tris, size_t(ntris) * 9 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&c->d_tri_obj, size_t(ntris));
+    if (e == hipSuccess) e = hipMemcpy(c->d_tris, tris, size_t(ntris) * 9 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_tri_obj, obj, size_t(ntris), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "set_triangles");
+  c->n_tris = ntris;
   return LBM_OK;
 }
 

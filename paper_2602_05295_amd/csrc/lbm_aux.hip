@@ -177,7 +177,16 @@ __global__ void debug_dither_kernel(int n, const uint32_t* __restrict__ idx, uin
 
 dim3 grid_for(int64_t N) { return dim3(uint32_t((N + 255) / 256)); }
 
+__global__ void set_counter_kernel(uint32_t* ctr, uint32_t v) {
+  if (threadIdx.x == 0) *ctr = v;
+}
+
 }  // namespace
+
+hipError_t launch_set_counter(uint32_t* ctr, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, ctr, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_set_moments(int fmt, const float* m, void* const out[10], const uint8_t* mask, int64_t N,
                               hipStream_t s) {

@@ -12,10 +12,12 @@ namespace lbm {
 // The pulled rest distributions, the same for every cell of the launch, are
 // evaluated once per workgroup into LDS.
 template <int FMT>
-__global__ void __launch_bounds__(256) boundary_fluid_kernel(StepParams a, const uint32_t* __restrict__ cells,
+__global__ void __launch_bounds__(256) boundary_fluid_kernel(StepParams ap, const uint32_t* __restrict__ cells,
                                                              const uint32_t* __restrict__ bits,
                                                              const uint32_t* __restrict__ yz,
                                                              const uint32_t* __restrict__ order, int count) {
+  StepParams a = ap;
+  a.key = step_key(ap);
   __shared__ float rest[27];
   if (threadIdx.x < 27) rest_links<FMT>(a, int(threadIdx.x), rest);
   __syncthreads();
@@ -29,10 +31,12 @@ __global__ void __launch_bounds__(256) boundary_fluid_kernel(StepParams a, const
 // step): per workgroup in LDS, then one double add per nonzero sum into
 // a.forces.
 template <int FMT>
-__global__ void __launch_bounds__(256) boundary_fluid_forces_kernel(StepParams a, const uint32_t* __restrict__ cells,
+__global__ void __launch_bounds__(256) boundary_fluid_forces_kernel(StepParams ap, const uint32_t* __restrict__ cells,
                                                                     const uint32_t* __restrict__ bits,
                                                                     const uint32_t* __restrict__ yz,
                                                                     const uint32_t* __restrict__ order, int count) {
+  StepParams a = ap;
+  a.key = step_key(ap);
   __shared__ float acc[256 * 6];
   __shared__ float rest[27];
   for (int k = int(threadIdx.x); k < 256 * 6; k += 256) acc[k] = 0.0f;
@@ -50,11 +54,11 @@ __global__ void __launch_bounds__(256) boundary_fluid_forces_kernel(StepParams a
 
 // Listed solid cells: one lane each.
 template <int FMT>
-__global__ void __launch_bounds__(256) boundary_solid_kernel(StepParams a, const uint32_t* __restrict__ cells,
+__global__ void __launch_bounds__(256) boundary_solid_kernel(StepParams ap, const uint32_t* __restrict__ cells,
                                                              int count) {
   const int e = int(blockIdx.x) * 256 + int(threadIdx.x);
   if (e >= count) return;
-  boundary_solid<FMT>(a, cells[e]);
+  boundary_solid<FMT>(ap, cells[e]);
 }
 
 namespace {

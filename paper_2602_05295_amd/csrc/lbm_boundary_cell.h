@@ -93,8 +93,6 @@ __device__ inline void store_cell_b(const StepParams& a, uint32_t cell, float dr
   }
 }
 
-// Post-collision coefficients of cell q (with the inflow velocity when
-// `inflow`: rho^p = rho^q, u^p = u_in, the non-equilibrium stress of q).
 // Post-collision moments of a cell: rho - 1, rho, j+, u+ and the
 // non-equilibrium stress rho (S+ - u+ u+) (App. A, with the body force if any).
 struct PostCell {
@@ -136,17 +134,6 @@ __device__ inline PostCell post_cell(const StepParams& a, uint32_t q) {
 __device__ inline void boundary_point_coeffs(const PostCell& x, const float up[3], float A[NA]) {
   const float jp[3] = {x.rho * up[0], x.rho * up[1], x.rho * up[2]};
   hermite_coeffs(x.dr, jp, up, x.Nn, A);
-}
-
-// Post-collision coefficients of cell q (with the inflow velocity when
-// `inflow`: rho^p = rho^q, u^p = u_in, the non-equilibrium stress of q).
-template <int FMT>
-__device__ inline void source_coeffs(const StepParams& a, uint32_t q, bool inflow, float A[NA]) {
-  const PostCell s = post_cell<FMT>(a, q);
-  if (inflow)
-    boundary_point_coeffs(s, a.u_in, A);
-  else
-    hermite_coeffs(s.dr, s.j, s.u, s.Nn, A);
 }
 
 // Velocity of object id at the midpoint p = x - c/2 of the link from cell
@@ -303,7 +290,7 @@ __device__ inline void boundary_fix(const StepParams& a, uint32_t e, uint32_t ce
   }
   if (b & BIT_INFLOW) {
     float Ain[NA];
-    source_coeffs<FMT>(a, cell, true, Ain);
+    boundary_point_coeffs(own, a.u_in, Ain);  // rho^p = rho^x, u^p = u_in, the stress of x
 #pragma unroll
     for (int cz = -1; cz <= 1; ++cz)
 #pragma unroll

@@ -126,6 +126,12 @@ __device__ inline void rest_codes(uint32_t* w) {
   }
 }
 
+// The dither key of a step: the host's, or in a captured step sequence the
+// one of the device-side step counter plus the step's place in the sequence.
+__device__ inline uint32_t step_key(const StepParams& a) {
+  return a.step_ctr ? dither_key(*a.step_ctr + a.step_off, a.seed, a.dither_mode) : a.key;
+}
+
 // Calls f.template operator()<FMT>() for the integer format fmt (runtime
 // dispatch over the instantiated formats); returns false for FMT_F32 or an
 // unknown value.

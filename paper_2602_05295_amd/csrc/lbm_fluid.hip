@@ -43,12 +43,6 @@
 
 namespace lbm {
 
-// Two planes per trip of the z march, with the paired buffers' roles swapped,
-// so no register is copied from one plane to the next (3% on both formats).
-#ifndef LBM_PLANE_PAIRS
-#define LBM_PLANE_PAIRS 1
-#endif
-
 constexpr int RW = 64;  // cells per row wavefront
 
 // LDS of a tile with TYR output rows (TYR + 2 row wavefronts).
@@ -142,8 +136,10 @@ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v -
 // the codes hold post-collision moments, which are reconstructed without a
 // collision, and the new moments are stored as FP32 post-stream moments.
 template <int FMT, int TYR, bool FORCE, bool MIXED = false, bool STREAM = false, bool FACES = false>
-__global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int ntx, int nty, int nseg, int nwg, int zt, int ntail) {
+__global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams ap, int ntx, int nty, int nseg, int nwg, int zt, int ntail) {
   constexpr int OUT = MIXED ? int(FMT_F32) : FMT;
+  StepParams a = ap;
+  a.key = step_key(ap);
   constexpr int NRW = TYR + 2;  // row wavefronts (with the two halo rows)
   __shared__ FluidLds<TYR> L;
 
@@ -349,34 +345,19 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams a, int
       }
     };
 
-    // The last step (plane zb) leaves the moments of plane zb - 1, whose
-    // bitmap words it loaded into lwB when it ran as the first plane of a
-    // trip (lwA otherwise, and always lwA in the one-plane loop).
-    bool last_in_b = false;
-    if constexpr (LBM_PLANE_PAIRS) {
-      // buffers at the start of a trip: state in bufA, fp(p - 2) in wA, fp(p - 1) in wB, f0(p - 1) in zA
-      for (int p = za - 1; p <= zb; p += 2) {
-        plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
-        // now fp(p - 1) in wB, fp(p) in wA, f0(p) in zB
-        if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA);
-        // now fp(p) in wA, fp(p + 1) in wB, f0(p + 1) in zA: the trip's starting roles
-      }
-      last_in_b = ((zb - za) & 1) != 0;  // plane zb ran first in its trip
-    } else {
-      // one plane per trip, the roles restored by copies
-      for (int p = za - 1; p <= zb; ++p) {
-        plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
-        bufA = bufB;
-#pragma unroll
-        for (int g = 0; g < 6; ++g) {
-          const float t = wA[g];
-          wA[g] = wB[g];
-          wB[g] = t;
-          zA[g] = zB[g];
-        }
-        lwA = lwB;
-      }
+    // Two planes per trip of the z march, with the paired buffers' roles
+    // swapped, so no register is copied from one plane to the next (3% on
+    // both formats).  The last step (plane zb) leaves the moments of plane
+    // zb - 1, whose bitmap words it loaded into lwB when it ran as the first
+    // plane of a trip (lwA otherwise).
+    // buffers at the start of a trip: state in bufA, fp(p - 2) in wA, fp(p - 1) in wB, f0(p - 1) in zA
+    for (int p = za - 1; p <= zb; p += 2) {
+      plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
+      // now fp(p - 1) in wB, fp(p) in wA, f0(p) in zB
+      if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA);
+      // now fp(p) in wA, fp(p + 1) in wB, f0(p + 1) in zA: the trip's starting roles
     }
+    const bool last_in_b = ((zb - za) & 1) != 0;  // plane zb ran first in its trip
     if (zb - 1 >= za) {
       if (last_in_b)
         store_plane(zb - 1, lwB);

@@ -93,8 +93,15 @@ struct StepParams {
   // om1 dev(N) is nq_s q + nq_c off the diagonal and nq_s q - nq_d (q_xx +
   // q_yy + q_zz) on it, with nq_s = om1 dN, nq_d = nq_s / 3, nq_c = om1 lo_N
   float nq_s, nq_d, nq_c;
-  uint32_t key;        // dither key of this step
+  uint32_t key;        // dither key of this step (when step_ctr is null)
   int dither;          // 0: round to nearest; else add the dither of `key`
+  // In a captured step sequence the key comes from a device-side step
+  // counter instead: dither_key(*step_ctr + step_off, seed, dither_mode), so
+  // the sequence can be replayed at any later step.
+  const uint32_t* step_ctr;
+  uint32_t step_off;
+  uint32_t seed;
+  int dither_mode;
   int stream_out;      // the fluid pass writes the new state with non-temporal stores (stream_out_state)
   float u_in[3];
   float hF[3];         // half the body force, F / 2 (App. A); zero without force
@@ -181,6 +188,24 @@ hipError_t launch_stream_mixed(const StepParams& p, int rows, hipStream_t s);
 hipError_t launch_mixed_links(const StepParams& p, const uint32_t* links, int nlinks, const uint32_t* cells,
                               const uint32_t* yz, const uint32_t* bits, hipStream_t s);
 hipError_t launch_requantize(const StepParams& p, int64_t N, hipStream_t s);
+// Obstacle meshes of the per-triangle solid correction (Alg. 3): n triangles,
+// 9 floats each (three vertices), and the object id of each.
+struct TriangleSet {
+  const float* tris;
+  const uint8_t* obj;
+  int n;
+  const uint4* lpack;     // the boundary list's packed bitmap (ListedCells::lpack)
+  const uint32_t* bits;   // flags of the listed fluid entries, in slot order
+};
+// Nearest-hit keys: winner[27 slot + i] = min over triangles meeting link i of
+// listed fluid entry `slot` of (t bits << 32 | triangle); the list's
+// nslots entries, filled first with ~0.
+hipError_t launch_triangle_winners(const StepParams& p, const TriangleSet& T, unsigned long long* winner,
+                                   int64_t nslots, hipStream_t s);
+// One step's corrections (p.in = the post-collision codes, p.out = the FP32
+// post-stream planes): each triangle corrects the links it wins.
+hipError_t launch_triangle_correction(const StepParams& p, const TriangleSet& T, const unsigned long long* winner,
+                                      hipStream_t s);
 
 // Boundary pass: the nfluid listed fluid cells (list order = slot order,
 // with their y | z << 16 in yz) take the fluid pass's moments from p.lc.side
@@ -209,5 +234,7 @@ hipError_t launch_get_moments(int fmt, const void* const in[10], float* m, const
 hipError_t launch_set_rest(int fmt, void* const out[10], int64_t N, hipStream_t s);
 hipError_t launch_health(int fmt, const void* const in[10], int64_t N, unsigned long long* bad, hipStream_t s);
 hipError_t launch_debug_dither(int n, const uint32_t* idx, uint32_t key, uint32_t* out, hipStream_t s);
+// *ctr = v (one thread), ordered on stream s: the step counter of captured sequences.
+hipError_t launch_set_counter(uint32_t* ctr, uint32_t v, hipStream_t s);
 
 }  // namespace lbm

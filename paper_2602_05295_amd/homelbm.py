@@ -62,6 +62,7 @@ class Options(ctypes.Structure):
         ("wall_rule", ctypes.c_int),
         ("track_forces", ctypes.c_int),
         ("pipeline", ctypes.c_int),
+        ("graph_steps", ctypes.c_int),
     ]
 
 
@@ -118,6 +119,7 @@ def lib():
     L.lbm_set_moments.argtypes = [vp, vp, i]
     L.lbm_set_equilibrium.argtypes = [vp, vp, vp, i]
     L.lbm_step.argtypes = [vp, i]
+    L.lbm_prepare.argtypes = [vp, i]
     L.lbm_step_into.argtypes = [vp, vp, vp]
     L.lbm_set_object.argtypes = [vp, i, vp, vp, vp]
     L.lbm_get_object_forces.argtypes = [vp, vp, i]
@@ -135,6 +137,7 @@ def lib():
     L.lbm_synchronize.argtypes = [vp]
     L.lbm_profile_steps.argtypes = [vp, i, P(ctypes.c_double), P(ctypes.c_double), P(i), P(i)]
     L.lbm_debug_dither.argtypes = [i, vp, ctypes.c_uint32, ctypes.c_uint32, i, vp]
+    L.lbm_set_triangles.argtypes = [vp, ctypes.c_int64, vp, vp]
     L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
     L.lbm_adjoint_step_noalloc.argtypes = [vp, vp, vp, vp]
     L.lbm_equilibrium_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -275,7 +278,7 @@ class HomeLBM:
         return o
 
     def set_options(self, dither_mode=None, seed=None, inflow=None, u_in=None, check_health=None, tile_rows=None,
-                    force=None, wall_rule=None, track_forces=None, pipeline=None):
+                    force=None, wall_rule=None, track_forces=None, pipeline=None, graph_steps=None):
         o = self.options()
         if dither_mode is not None:
             o.dither_mode = int(dither_mode)
@@ -297,12 +300,24 @@ class HomeLBM:
             o.track_forces = int(bool(track_forces))
         if pipeline is not None:
             o.pipeline = int(pipeline)
+        if graph_steps is not None:
+            o.graph_steps = int(graph_steps)
         self._check(lib().lbm_set_options(self._h, ctypes.byref(o)))
 
     def set_object(self, oid, center=(0.0, 0.0, 0.0), velocity=(0.0, 0.0, 0.0), omega=(0.0, 0.0, 0.0)):
         """Wall motion of solid object oid (its mask value) and its torque center."""
         f3 = lambda v: (ctypes.c_float * 3)(*[float(x) for x in v])
         self._check(lib().lbm_set_object(self._h, int(oid), f3(center), f3(velocity), f3(omega)))
+
+    def set_triangles(self, tris, obj):
+        """Obstacle meshes of wall rule 2: tris (T, 9) float32 vertices, obj (T,)
+        uint8 object ids (host arrays)."""
+        t = np.ascontiguousarray(tris, dtype=np.float32).reshape(-1, 9)
+        o = np.ascontiguousarray(obj, dtype=np.uint8).reshape(-1)
+        if o.size != t.shape[0]:
+            raise ValueError("one object id per triangle")
+        self._check(lib().lbm_set_triangles(self._h, int(t.shape[0]), t.ctypes.data_as(ctypes.c_void_p),
+                                            o.ctypes.data_as(ctypes.c_void_p)))
 
     def profile_stages(self, n):
         """Runs n steps; summed device ms of the fluid / stream pass, the boundary
@@ -362,6 +377,10 @@ class HomeLBM:
     # -- stepping
     def step(self, n=1):
         self._check(lib().lbm_step(self._h, int(n)))
+
+    def prepare(self, n):
+        """Capture ahead of time what step(n) replays (no step is taken)."""
+        self._check(lib().lbm_prepare(self._h, int(n)))
 
     def step_into(self, raw_in, raw_out):
         """One step from the raw state raw_in to raw_out (device tensors in the

@@ -26,13 +26,14 @@ def test_options_struct_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"(\w+)\s+(\w+)(\[\d+\])?;", body)
     assert [f[1] for f in fields] == [f[0] for f in homelbm.Options._fields_]
-    assert ctypes.sizeof(homelbm.Options) == 4 * 14
+    assert ctypes.sizeof(homelbm.Options) == 4 * 15
 
 
 def test_default_options_without_gpu():
     o = homelbm.Options()
     assert homelbm.lib().lbm_default_options(ctypes.byref(o)) == 0
     assert o.dither_mode == homelbm.DITHER_PER_STEP and o.check_health == 1 and o.inflow == 0
+    assert o.graph_steps == 256
 
 
 def test_create_rejects_bad_arguments_before_touching_the_device():
