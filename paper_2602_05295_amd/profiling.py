@@ -5,6 +5,7 @@ folder.
     python -m paper_2602_05295_amd.profiling traffic <fetch.db> <write.db> --copy-bytes B
                                              --kernel NAME=FMT:BYTES_PER_LAUNCH [...] [--json OUT]
     python -m paper_2602_05295_amd.profiling valu <sq.db> --kernel NAME=FMT [...] --json OUT
+    python -m paper_2602_05295_amd.profiling sq <sq.db> [<sq2.db> ...] --kernel NAME=LABEL:CELLS [...]
 
 `trace` prints the per-kernel table of a --kernel-trace --stats run.
 `traffic` turns two --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch,
@@ -14,6 +15,8 @@ copy profiled in the same run (the largest __amd_rocclr_copyBuffer
 dispatches): the copy moves B bytes each way.
 `valu` records SQ_INSTS_VALU (wave instructions) per dispatch of the named
 kernels, for the VALU-issue roofline bench.py reports beside the HBM one.
+`sq` tabulates the SQ counters of one or more --pmc runs per named kernel
+(means per dispatch): instruction mix, VALU per cell, waiting.
 """
 from __future__ import annotations
 
@@ -79,6 +82,9 @@ def main(argv=None):
     q.add_argument("--kernel", action="append", default=[], help="NAME=FMT")
     q.add_argument("--json", required=True)
     q.add_argument("--kernel-hash", default=None)
+    c = sub.add_parser("sq")
+    c.add_argument("db", nargs="+", help="--pmc runs holding SQ_ / GRBM_ counters")
+    c.add_argument("--kernel", action="append", default=[], help="NAME=LABEL:CELLS_PER_LAUNCH")
     r = sub.add_parser("traffic")
     r.add_argument("fetch_db")
     r.add_argument("write_db")
@@ -103,6 +109,33 @@ def main(argv=None):
         with open(a.json, "w") as fh:
             json.dump(res, fh, indent=1)
             fh.write("\n")
+        return 0
+    if a.cmd == "sq":
+        # mean per dispatch of every counter found, then the derived columns
+        means = defaultdict(dict)
+        for db in a.db:
+            con = sqlite3.connect(db)
+            names = {row[0] for row in con.execute("select distinct counter_name from counters_collection")}
+            con.close()
+            for cn in sorted(names):
+                for kn, vals in counter_per_dispatch_named(db, cn).items():
+                    means[kn][cn] = sum(vals) / len(vals)
+        print("| kernel | waves | VALU instr | VALU / cell | LDS instr | VMEM rd instr | wait | VALU active | "
+              "LDS bank conflicts |")
+        print("|---|---:|---:|---:|---:|---:|---:|---:|---:|")
+        for spec in a.kernel:
+            name, rest = spec.rsplit("=", 1)
+            label, cells = rest.rsplit(":", 1)
+            m = means.get(name)
+            if not m:
+                print(f"missing kernel {name}", file=sys.stderr)
+                return 1
+            g = lambda k: m.get(k, float("nan"))
+            wc = g("SQ_WAVE_CYCLES")
+            print(f"| `{name}` ({label}) | {g('SQ_WAVES'):.0f} | {g('SQ_INSTS_VALU') / 1e6:.1f} M | "
+                  f"{g('SQ_INSTS_VALU') * 64 / int(cells):.0f} | {g('SQ_INSTS_LDS') / 1e6:.1f} M | "
+                  f"{g('SQ_INSTS_VMEM_RD') / 1e6:.2f} M | {g('SQ_WAIT_INST_ANY') / wc:.2f} | "
+                  f"{g('SQ_ACTIVE_INST_VALU') / wc:.2f} | {g('SQ_LDS_BANK_CONFLICT'):.0f} |")
         return 0
     if a.cmd == "trace":
         print("| kernel | calls | total (us) | average (us) | share |")
