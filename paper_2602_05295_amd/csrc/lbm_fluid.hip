@@ -45,13 +45,24 @@ namespace lbm {
 
 constexpr int RW = 64;  // cells per row wavefront
 
-// LDS of a tile with TYR output rows (TYR + 2 row wavefronts).
+// LDS of a tile with TYR output rows (TYR + 2 row wavefronts), two copies of
+// everything, used by alternate planes: the plane step has one barrier, so a
+// wavefront can write plane p + 1's movers while another still reads plane
+// p's.
 template <int TYR>
 struct FluidLds {
-  float ly[16][TYR + 2][RW];  // y movers (+, -) of 8 groups, row wavefronts
-  float lyc[16][2][16];       // y movers of the two halo columns
-  float lx[18][TYR][RW + 2];  // x movers (+, -) of 9 groups, with halo columns at 0 and RW + 1
+  float ly[2][16][TYR + 2][RW];  // y movers (+, -) of 8 groups, row wavefronts
+  float le[2][9][2][TYR];        // x movers entering the tile: + from x0 - 1, - from x0 + 64, of 9 groups
 };
+
+// Lane moves (DPP): lane l takes v of lane l - 1 (SHR) or l + 1 (SHL) across
+// the wavefront (WAVE) or within rows of 16 lanes (ROW); a lane without a
+// source keeps `edge`.
+constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130, DPP_ROW_SHR1 = 0x111, DPP_ROW_SHL1 = 0x101;
+template <int CTRL>
+__device__ inline float lane_move(float edge, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 
 // The stored words of one cell: ten floats, or the format's code words.
 template <int FMT, bool F = (FMT == FMT_F32)>
@@ -185,6 +196,9 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams ap, in
       za = zt;
       zb = nz;
     }
+    // the last plane step of the previous item may still be reading the LDS
+    // buffer that this item's first step writes
+    __syncthreads();
     const int x0 = (t % ntx) * RW, y0 = (t / ntx) * TYR;
     const int gx = x0 + dx, gy = y0 - 1 + r;
     // open x faces (FACES; not in the mixed pipeline, which keeps the periodic
@@ -257,65 +271,69 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams ap, in
       recon2(A[A101], A[A111], f0[5], fp[5], fm[5]);           // (1,1)
       recon1(A[A201], f0[6], fp[6], fm[6]);                    // (2,1)
       recon1(A[A102], f0[7], fp[7], fm[7]);                    // (1,2)
+      const int par = p & 1;
       if (!colw) {
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
-          L.ly[2 * g][r][lane] = fp[g];
-          L.ly[2 * g + 1][r][lane] = fm[g];
+          L.ly[par][2 * g][r][lane] = fp[g];
+          L.ly[par][2 * g + 1][r][lane] = fm[g];
         }
-      } else if (active) {
+      } else {
+        // The halo columns x0 - 1 (side 0) and x0 + 64 (side 1), row r in
+        // lane r of a 16-lane row: their y pass by lane moves within the
+        // wavefront (full exec, so every source lane is live), then the x
+        // movers that enter the tile, published before the barrier.
+        float Y[8][3];
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          L.lyc[2 * g][side][r] = fp[g];
-          L.lyc[2 * g + 1][side][r] = fm[g];
-        }
-      }
-      __syncthreads();
-
-      float Y[8][3];  // Y[g][b] = channel (n, b, l) of y-group g = (n, l)
-      float x0v[9], xp[9], xm[9];
-      if (inner) {
-        if (!colw) {
+        for (int g = 0; g < 8; ++g)
+          proj3(f0[g], lane_move<DPP_ROW_SHR1>(0.0f, fp[g]), lane_move<DPP_ROW_SHL1>(0.0f, fm[g]), Y[g][0], Y[g][1],
+                Y[g][2]);
+        if (active && inner) {
+          float x0v[9], xp[9], xm[9];
 #pragma unroll
-          for (int g = 0; g < 8; ++g)
-            proj3(f0[g], L.ly[2 * g][r - 1][lane], L.ly[2 * g + 1][r + 1][lane], Y[g][0], Y[g][1], Y[g][2]);
-        } else {
-#pragma unroll
-          for (int g = 0; g < 8; ++g)
-            proj3(f0[g], L.lyc[2 * g][side][r - 1], L.lyc[2 * g + 1][side][r + 1], Y[g][0], Y[g][1], Y[g][2]);
-        }
-        // ---- x pass: groups (b, l) with inputs n = 0, 1, 2 along x
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb) {
-          recon3(Y[0][bb], Y[1][bb], Y[3][bb], x0v[3 * bb + 0], xp[3 * bb + 0], xm[3 * bb + 0]);  // l = 0
-          recon3(Y[2][bb], Y[5][bb], Y[6][bb], x0v[3 * bb + 1], xp[3 * bb + 1], xm[3 * bb + 1]);  // l = 1
-          recon2(Y[4][bb], Y[7][bb], x0v[3 * bb + 2], xp[3 * bb + 2], xm[3 * bb + 2]);            // l = 2
-        }
-        if (!colw) {
-#pragma unroll
-          for (int h = 0; h < 9; ++h) {
-            L.lx[2 * h][r - 1][lane + 1] = xp[h];
-            L.lx[2 * h + 1][r - 1][lane + 1] = xm[h];
+          for (int bb = 0; bb < 3; ++bb) {
+            recon3(Y[0][bb], Y[1][bb], Y[3][bb], x0v[3 * bb + 0], xp[3 * bb + 0], xm[3 * bb + 0]);  // l = 0
+            recon3(Y[2][bb], Y[5][bb], Y[6][bb], x0v[3 * bb + 1], xp[3 * bb + 1], xm[3 * bb + 1]);  // l = 1
+            recon2(Y[4][bb], Y[7][bb], x0v[3 * bb + 2], xp[3 * bb + 2], xm[3 * bb + 2]);            // l = 2
           }
-        } else if (active) {
           if (side == 0) {
 #pragma unroll
-            for (int h = 0; h < 9; ++h) L.lx[2 * h][r - 1][0] = ghost_in ? 0.0f : xp[h];
+            for (int h = 0; h < 9; ++h) L.le[par][h][0][r - 1] = ghost_in ? 0.0f : xp[h];
           } else {
 #pragma unroll
-            for (int h = 0; h < 9; ++h) L.lx[2 * h + 1][r - 1][RW + 1] = xm[h];
+            for (int h = 0; h < 9; ++h) L.le[par][h][1][r - 1] = xm[h];
           }
         }
       }
       __syncthreads();
 
       if (compute) {
+        float Y[8][3];  // Y[g][b] = channel (n, b, l) of y-group g = (n, l)
+#pragma unroll
+        for (int g = 0; g < 8; ++g)
+          proj3(f0[g], L.ly[par][2 * g][r - 1][lane], L.ly[par][2 * g + 1][r + 1][lane], Y[g][0], Y[g][1], Y[g][2]);
+        // ---- x pass: groups (b, l) with inputs n = 0, 1, 2 along x, one y
+        // channel b at a time; the movers cross lanes by DPP, and the lanes at
+        // the tile's edges take those of the halo columns
         float X00[3], X10[3], X20[3], X01[3], X11[3], X02[3];  // Xab[l] = channel (a, b, l)
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          proj3(x0v[l], L.lx[2 * l][r - 1][lane], L.lx[2 * l + 1][r - 1][lane + 2], X00[l], X10[l], X20[l]);
-          proj2(x0v[3 + l], L.lx[2 * (3 + l)][r - 1][lane], L.lx[2 * (3 + l) + 1][r - 1][lane + 2], X01[l], X11[l]);
-          X02[l] = proj1(x0v[6 + l], L.lx[2 * (6 + l)][r - 1][lane], L.lx[2 * (6 + l) + 1][r - 1][lane + 2]);
+        for (int bb = 0; bb < 3; ++bb) {
+          float g0[3], gp[3], gm[3];
+          recon3(Y[0][bb], Y[1][bb], Y[3][bb], g0[0], gp[0], gm[0]);  // l = 0
+          recon3(Y[2][bb], Y[5][bb], Y[6][bb], g0[1], gp[1], gm[1]);  // l = 1
+          recon2(Y[4][bb], Y[7][bb], g0[2], gp[2], gm[2]);            // l = 2
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const int h = 3 * bb + l;
+            const float Fp = lane_move<DPP_WAVE_SHR1>(L.le[par][h][0][r - 1], gp[l]);
+            const float Fm = lane_move<DPP_WAVE_SHL1>(L.le[par][h][1][r - 1], gm[l]);
+            if (bb == 0)
+              proj3(g0[l], Fp, Fm, X00[l], X10[l], X20[l]);
+            else if (bb == 1)
+              proj2(g0[l], Fp, Fm, X01[l], X11[l]);
+            else
+              X02[l] = proj1(g0[l], Fp, Fm);
+          }
         }
         // ---- z pass: groups (a, b) = (0,0) (1,0) (0,1) (2,0) (1,1) (0,2), inputs l = 0, 1, 2
         float zf0[6], zfp[6], zfm[6];
