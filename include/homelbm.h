@@ -92,8 +92,13 @@ typedef struct lbm_options {
   int check_health;   /* 1 (default): lbm_step scans the state once at its end and
                          returns LBM_ERR_UNSTABLE if any stored value is non-finite
                          (FP32) or any code sits at 0 or its maximum (integer formats) */
-  int tile_rows;      /* fluid-pass tile height: 0 (default) picks one from the grid
-                         shape; 8, 10, 12 or 13 force it.  Results do not depend on it. */
+  int tile_rows;      /* fluid-pass tile height: 8, 10, 12 or 13 force it.  0 (default):
+                         the first lbm_step, lbm_step_into, lbm_prepare or lbm_profile_*
+                         call (after the boundary list is built) times the fluid pass
+                         once per height, three rounds, from the current state into the
+                         other buffer (the state is unchanged; synchronous), and keeps
+                         the fastest; changing inflow, force or tile_rows times again.
+                         Results do not depend on the height. */
   float force[3];     /* uniform body force F per cell and step, lattice units (App. A
                          with its force terms; the stored momentum holds F/2 as in
                          Eq. rho_u_stress).  Default 0; each |F_a| <= 0.01.  Not
@@ -196,7 +201,8 @@ int lbm_step(lbm_ctx* ctx, int n);
 /*
  * Does ahead of time, without advancing the state, what the first
  * lbm_step(ctx, n) would do before its first kernel: builds the boundary list
- * if needed and, with graph_steps > 0 and pipeline 0, captures and
+ * if needed, times the tile heights (tile_rows = 0), and, with graph_steps > 0
+ * and pipeline 0, captures and
  * instantiates the step sequences that lbm_step(ctx, n) replays, from either
  * buffer, so that a later lbm_step(ctx, n) only launches them.  Synchronous;
  * the captures are dropped like any others (options or boundary list
@@ -357,7 +363,9 @@ int lbm_profile_steps(lbm_ctx* ctx, int n, double* fluid_ms, double* boundary_ms
 
 /*
  * Host-only: the fluid pass's work split for a grid, without touching the
- * device.  tile_rows as in lbm_options; cus = compute units of the device.
+ * device.  tile_rows 8, 10, 12 or 13, or 0 for the planner's own choice (a
+ * context with tile_rows = 0 times the heights instead); cus = compute units
+ * of the device.
  * out = {tile rows, tiles along x (64 cells each), tiles along y, z segments
  * per tile, workgroups launched, tail planes, tail workgroups}.  The z range
  * below the tail, [0, nz - tail), is cut into the segments: work item q

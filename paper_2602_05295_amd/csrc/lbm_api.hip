@@ -56,6 +56,8 @@ struct lbm_ctx {
   float* d_tris = nullptr;
   uint8_t* d_tri_obj = nullptr;
   int64_t n_tris = 0;
+  // tile height of the fluid pass picked by timing (options.tile_rows = 0); 0 until then
+  int tuned_rows = 0;
   unsigned long long* d_winner = nullptr;  // nearest-hit key per listed fluid entry and link
   bool winners_built = false;
   bool flags_valid = false;
@@ -250,10 +252,14 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
 }
 
 // The kernels of one step on stream s: fluid pass then boundary pass.
+// The fluid pass's tile height: the caller's, else the timed choice, else
+// the planner's (before the timing has run).
+int fluid_rows(const lbm_ctx* c) { return c->opt.tile_rows != 0 ? c->opt.tile_rows : c->tuned_rows; }
+
 int launch_pass(lbm_ctx* c, const StepParams& p, hipStream_t s, hipEvent_t ev[4]) {
   hipError_t e = hipSuccess;
   if (ev) e = hipEventRecord(ev[0], s);
-  if (e == hipSuccess) e = launch_fluid(c->fmt, p, c->opt.tile_rows, s);
+  if (e == hipSuccess) e = launch_fluid(c->fmt, p, fluid_rows(c), s);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
   if (e != hipSuccess) return hip_fail(c, e, "fluid pass");
   const int64_t n = c->n_fluid_b + c->n_solid_b;
@@ -266,6 +272,43 @@ int launch_pass(lbm_ctx* c, const StepParams& p, hipStream_t s, hipEvent_t ev[4]
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
+  return LBM_OK;
+}
+
+// With tile_rows = 0: times the fluid pass once for every tile height, from
+// the current state into the other buffer (the state is unchanged), and keeps
+// the fastest.  The heights take turns, three rounds after two warm-up
+// launches, and each keeps its best time: a new context's first launches run
+// slow, and no height should take them all.  Every tile height gives the
+// same result, so the choice changes the speed only.
+int tune_rows(lbm_ctx* c) {
+  if (c->opt.tile_rows != 0 || c->tuned_rows != 0 || c->opt.pipeline == 1) return LBM_OK;
+  const StepParams p = step_params(c, c->buf[c->cur], c->buf[1 - c->cur]);
+  constexpr int NR = int(sizeof(kFluidTileRows) / sizeof(kFluidTileRows[0]));
+  float best[NR];
+  for (float& b : best) b = 3.0e38f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = launch_fluid(c->fmt, p, kFluidTileRows[k % NR], c->stream);
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+    for (int i = 0; i < NR && e == hipSuccess; ++i) {
+      e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) e = launch_fluid(c->fmt, p, kFluidTileRows[i], c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) best[i] = std::min(best[i], ms);
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "timing the tile heights");
+  int k = 0;
+  for (int i = 1; i < NR; ++i)
+    if (best[i] < best[k]) k = i;
+  c->tuned_rows = kFluidTileRows[k];
+  drop_graphs(c);  // none should hold another height, but captures made before the timing would
   return LBM_OK;
 }
 
@@ -632,6 +675,10 @@ int lbm_set_options(lbm_ctx* c, const lbm_options* o) {
   }
   const int old_inflow = c->opt.inflow, old_pipeline = c->opt.pipeline;
   drop_graphs(c);  // captured steps hold the old options
+  // another kernel variant may prefer another tile height
+  const bool forced = c->opt.force[0] != 0.0f || c->opt.force[1] != 0.0f || c->opt.force[2] != 0.0f;
+  const bool forced_new = o->force[0] != 0.0f || o->force[1] != 0.0f || o->force[2] != 0.0f;
+  if (old_inflow != o->inflow || forced != forced_new || o->tile_rows != c->opt.tile_rows) c->tuned_rows = 0;
   if (o->wall_rule != c->opt.wall_rule) c->links_built = false;  // wall rule 2 keeps only the face links
   c->opt = *o;
   c->opt.pipeline = old_pipeline;
@@ -717,6 +764,10 @@ int lbm_step(lbm_ctx* c, int n) {
     const int r = build_list(c);
     if (r != LBM_OK) return r;
   }
+  if (n > 0) {
+    const int r = tune_rows(c);
+    if (r != LBM_OK) return r;
+  }
   const bool graphs = c->opt.graph_steps > 0 && c->opt.pipeline != 1;
   int left = n;
   while (left > 0) {
@@ -778,6 +829,10 @@ int lbm_prepare(lbm_ctx* c, int n) {
     const int r = build_list(c);
     if (r != LBM_OK) return r;
   }
+  {
+    const int r = tune_rows(c);
+    if (r != LBM_OK) return r;
+  }
   const int G = c->opt.graph_steps;
   if (G <= 0 || c->opt.pipeline == 1) return LBM_OK;
   // lbm_step(n) replays sequences of min(n, G) steps and, past G, one of the
@@ -836,6 +891,10 @@ int lbm_step_into(lbm_ctx* c, const void* in, void* out) {
   if (a < b + n && b < a + n) return fail(c, LBM_ERR_INVALID_ARG, "in and out overlap");
   if (!c->list_built) {
     const int r = build_list(c);
+    if (r != LBM_OK) return r;
+  }
+  {
+    const int r = tune_rows(c);
     if (r != LBM_OK) return r;
   }
   return enqueue_pass(c, in, out, nullptr);
@@ -943,6 +1002,10 @@ int lbm_profile_stages(lbm_ctx* c, int n, double ms[3]) {
     if (r != LBM_OK) return r;
   }
   const bool mixed = c->opt.pipeline == 1;
+  if (n > 0) {
+    const int r = tune_rows(c);
+    if (r != LBM_OK) return r;
+  }
   const bool has_b = mixed || (c->n_fluid_b + c->n_solid_b) > 0;
   std::vector<hipEvent_t> ev(size_t(6) * n);
   hipError_t e = hipSuccess;
