@@ -38,6 +38,10 @@ METRIC = "MLUPS & % HBM peak, fp32 vs 16-bit moments; adjoint/forward time ratio
 HBM_PEAK_GBS = 8000.0
 N = 256
 TAU = 0.51
+# fluid-pass tile height of the 256^3 legs and the channel: 0 lets each
+# context time the heights (the default); a profiling run pins one so that its
+# counters are taken on a known kernel
+TILE_ROWS = 0
 BYTES_PER_CELL = {"q16": 40, "fp32": 80}   # one state read + one state written
 KERNEL_SOURCES = ["paper_2602_05295_amd/csrc/lbm_fluid.hip", "paper_2602_05295_amd/csrc/lbm_device.h",
                   "paper_2602_05295_amd/csrc/lbm_codec.h", "paper_2602_05295_amd/csrc/lbm_internal.h"]
@@ -133,7 +137,7 @@ def run_format(fmt, rho_d, u_d, steps, warmup):
     from paper_2602_05295_amd.homelbm import HomeLBM
     stream = torch.cuda.current_stream()
     with HomeLBM((N, N, N), TAU, fmt=fmt, stream=stream.cuda_stream) as s:
-        s.set_options(check_health=False, dither_mode=1, seed=0)
+        s.set_options(check_health=False, dither_mode=1, seed=0, tile_rows=TILE_ROWS)
         s.set_equilibrium(rho_d, u_d)
         # capture the step sequences that the warm-up and the timed call replay
         s.prepare(warmup)
@@ -225,7 +229,7 @@ def channel(steps=20):
     rho = torch.ones((nz, ny, nx), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     with HomeLBM((nx, ny, nz), 0.52, mask=mask, fmt="q16", stream=stream.cuda_stream) as s:
-        s.set_options(check_health=False, inflow=True, u_in=(0.08, 0.0, 0.0))
+        s.set_options(check_health=False, inflow=True, u_in=(0.08, 0.0, 0.0), tile_rows=TILE_ROWS)
         s.set_equilibrium(rho, u)
         del u, rho
         s.prepare(5)
@@ -584,10 +588,14 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=None, help="steps of the --only workload")
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip the plain-copy ceiling (and its device warm-up) before the timed legs")
+    ap.add_argument("--tile-rows", type=int, default=0, choices=[0, 8, 10, 12, 13],
+                    help="fluid-pass tile height of the 256^3 legs and the channel (0: timed per context)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (the reference kernel that "
                          "scales hardware byte counters)")
     args = ap.parse_args()
+    global TILE_ROWS
+    TILE_ROWS = args.tile_rows
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
