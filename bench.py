@@ -25,6 +25,7 @@ import argparse
 import faulthandler
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -58,9 +59,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _hash_checked(path: str, fmt: str, key: str):
+def _profiled_rows(kernel_name: str) -> int:
+    """Tile height of a profiled fluid-kernel name, fluid_kernel<FMT, ROWS, ...>."""
+    m = re.search(r"fluid_kernel<\d+, (\d+),", kernel_name)
+    return int(m.group(1)) if m else 0
+
+
+def _hash_checked(path: str, fmt: str, key: str, rows: int):
     """The committed counter summary's `key` for `fmt`, or None when the file
-    is missing or was taken on a different kernel source."""
+    is missing, was taken on a different kernel source or on another tile
+    height than the `rows` the timed context used."""
     try:
         with open(path) as fh:
             t = json.load(fh)
@@ -68,14 +76,17 @@ def _hash_checked(path: str, fmt: str, key: str):
         return None
     if t.get("kernel_hash") != kernel_hash() or fmt not in t.get("formats", {}):
         return None
-    return t["formats"][fmt][key]
+    f = t["formats"][fmt]
+    if _profiled_rows(f.get("kernel", "")) != rows:
+        return None
+    return f[key]
 
 
-def valu_roofline(fmt: str, kernel_ms: float):
+def valu_roofline(fmt: str, kernel_ms: float, rows: int):
     """VALU-issue roofline of the fluid pass: measured wave instructions per
     launch (rocprofv3 SQ_INSTS_VALU) / mean launch time, against 256 CUs x 4
     SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction (packed FP32 off)."""
-    n = _hash_checked(VALU_FILE, fmt, "valu_instructions_per_launch")
+    n = _hash_checked(VALU_FILE, fmt, "valu_instructions_per_launch", rows)
     if n is None:
         return None
     achieved = n / (kernel_ms * 1e-3) / 1e9
@@ -83,17 +94,11 @@ def valu_roofline(fmt: str, kernel_ms: float):
             "frac": round(achieved / VALU_PEAK_G, 4), "instructions_per_launch": n}
 
 
-def measured_traffic(fmt: str):
+def measured_traffic(fmt: str, rows: int):
     """HBM bytes per fluid launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on a different kernel source."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_hash") != kernel_hash() or fmt not in t.get("formats", {}):
-        return None
-    return t["formats"][fmt]["hbm_bytes_per_launch"]
+    or None when it is missing or was taken on a different kernel source or
+    tile height."""
+    return _hash_checked(TRAFFIC_FILE, fmt, "hbm_bytes_per_launch", rows)
 
 
 def copy_ceiling(nbytes=1 << 30, seconds=0.5):
@@ -156,6 +161,7 @@ def run_format(fmt, rho_d, u_d, steps, warmup):
         # per-launch kernel time of the fluid pass (events around each launch)
         prof = s.profile_steps(min(steps, 200))
         state_bytes, _ = s.memory_bytes()
+        rows = s.tile_rows
     cells = N ** 3
     fluid_ms = prof["fluid_ms"] / max(prof["fluid_launches"], 1)
     achieved = cells * BYTES_PER_CELL[fmt] / (fluid_ms * 1e-3) / 1e9
@@ -167,6 +173,7 @@ def run_format(fmt, rho_d, u_d, steps, warmup):
         "achieved_GBs": achieved,
         "hbm_frac": achieved / HBM_PEAK_GBS,
         "state_bytes": state_bytes,
+        "tile_rows": rows,
         "unhealthy_values": int(bad),
     }
 
@@ -244,6 +251,7 @@ def channel(steps=20):
         ms = ev0.elapsed_time(ev1) / steps
         prof = s.profile_steps(steps)
         nf, ns = s.boundary_counts()
+        rows = s.tile_rows
         bad = s.check()
         # the same scene in the paper's mixed-precision pipeline (Sec. 5.3):
         # stream pass into FP32, link corrections with atomicAdd, requantize
@@ -266,7 +274,7 @@ def channel(steps=20):
     return {"config": "1000x400x400 channel, 16-bit, tau 0.52, inflow 0.08 into fluid at rest, 300 obstacles",
             "solid_fraction": round(float(mask.mean()), 4), "boundary_fluid_cells": nf, "boundary_solid_cells": ns,
             "mlups": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
-            "fluid_kernel_ms": round(prof["fluid_ms"] / prof["fluid_launches"], 4),
+            "fluid_kernel_ms": round(prof["fluid_ms"] / prof["fluid_launches"], 4), "tile_rows": rows,
             "boundary_kernel_ms": round(prof["boundary_ms"] / max(prof["boundary_launches"], 1), 4),
             # the fluid pass's algorithmic bytes (one 16-bit state read and written, 40 B per cell)
             "fluid_GBs": round(cells * 40 / (prof["fluid_ms"] / prof["fluid_launches"] * 1e-3) / 1e9, 1),
@@ -671,8 +679,8 @@ def main():
         print(json.dumps({k: v for k, v in res.items()}), flush=True)
         return
     q = res["q16"]
-    traffic = measured_traffic("q16")
-    traffic32 = measured_traffic("fp32")
+    traffic = measured_traffic("q16", q["tile_rows"])
+    traffic32 = measured_traffic("fp32", res["fp32"]["tile_rows"])
     line = {
         "metric": METRIC,
         "value": round(q["mlups"], 1),
@@ -693,8 +701,8 @@ def main():
                      "frac": round(q["hbm_frac"], 4),
                      "traffic": None if traffic is None else round(traffic / (q["fluid_kernel_ms"] * 1e-3) / 1e9, 1),
                      "traffic_bytes_per_launch": traffic, "algorithmic_bytes_per_launch": N ** 3 * BYTES_PER_CELL["q16"],
-                     "kernel": "fluid_kernel<Q16>", "bytes_per_cell": BYTES_PER_CELL["q16"]},
-        "roofline_valu": valu_roofline("q16", q["fluid_kernel_ms"]),
+                     "kernel": f"fluid_kernel<Q16, {q['tile_rows']} rows>", "bytes_per_cell": BYTES_PER_CELL["q16"]},
+        "roofline_valu": valu_roofline("q16", q["fluid_kernel_ms"], q["tile_rows"]),
         "copy_ceiling": None if ceiling is None else dict(ceiling, fluid_frac_of_copy=round(q["achieved_GBs"] / ceiling["GBs"], 4)),
         "fp32": {"value": round(res["fp32"]["mlups"], 1), "unit": "MLUPS",
                  "ms_per_step": round(res["fp32"]["ms_per_step"], 5),
@@ -703,8 +711,9 @@ def main():
                               "traffic": None if traffic32 is None else
                               round(traffic32 / (res["fp32"]["fluid_kernel_ms"] * 1e-3) / 1e9, 1),
                               "traffic_bytes_per_launch": traffic32,
-                              "kernel": "fluid_kernel<F32>", "bytes_per_cell": BYTES_PER_CELL["fp32"]},
-                 "roofline_valu": valu_roofline("fp32", res["fp32"]["fluid_kernel_ms"])},
+                              "kernel": f"fluid_kernel<F32, {res['fp32']['tile_rows']} rows>",
+                              "bytes_per_cell": BYTES_PER_CELL["fp32"]},
+                 "roofline_valu": valu_roofline("fp32", res["fp32"]["fluid_kernel_ms"], res["fp32"]["tile_rows"])},
         "memory_ratio_q16_fp32": res["q16"]["state_bytes"] / res["fp32"]["state_bytes"],
         "adjoint_forward_ratio": extras.get("adjoint", {}).get("ratio"),
         "adjoint": extras.get("adjoint"),

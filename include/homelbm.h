@@ -275,6 +275,13 @@ int lbm_memory_bytes(const lbm_ctx* ctx, size_t* state_bytes, size_t* total_byte
 /* Sizes of the boundary list: fluid cells recomputed by the boundary pass and solid cells reset to rest. */
 int lbm_boundary_counts(const lbm_ctx* ctx, int64_t* fluid_cells, int64_t* solid_cells);
 
+/*
+ * The fluid pass's tile height in use (see tile_rows in lbm_options): the
+ * option when set, else the height the context timed as fastest, else 0
+ * (not timed yet: the planner chooses).  Errors: LBM_ERR_INVALID_ARG.
+ */
+int lbm_tile_rows(const lbm_ctx* ctx, int* rows);
+
 /* Scans the state now; *bad receives the number of offending values (see check_health). */
 int lbm_check(lbm_ctx* ctx, uint64_t* bad);
 

@@ -982,6 +982,12 @@ int lbm_boundary_counts(const lbm_ctx* c, int64_t* fl, int64_t* so) {
   return LBM_OK;
 }
 
+int lbm_tile_rows(const lbm_ctx* c, int* rows) {
+  if (!c || !rows) return fail(const_cast<lbm_ctx*>(c), LBM_ERR_INVALID_ARG, "NULL argument");
+  *rows = fluid_rows(c);
+  return LBM_OK;
+}
+
 int lbm_check(lbm_ctx* c, uint64_t* bad) {
   if (!c || !bad) return fail(c, LBM_ERR_INVALID_ARG, "NULL argument");
   const int r = scan_health(c, bad);

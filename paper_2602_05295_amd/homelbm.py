@@ -133,6 +133,7 @@ def lib():
     L.lbm_set_step_count.argtypes = [vp, ctypes.c_uint64]
     L.lbm_memory_bytes.argtypes = [vp, P(sz), P(sz)]
     L.lbm_boundary_counts.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    L.lbm_tile_rows.argtypes = [vp, P(ctypes.c_int)]
     L.lbm_check.argtypes = [vp, P(ctypes.c_uint64)]
     L.lbm_synchronize.argtypes = [vp]
     L.lbm_profile_steps.argtypes = [vp, i, P(ctypes.c_double), P(ctypes.c_double), P(i), P(i)]
@@ -415,6 +416,13 @@ class HomeLBM:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().lbm_boundary_counts(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    @property
+    def tile_rows(self):
+        """The fluid pass's tile height in use (0 before the context has timed them)."""
+        r = ctypes.c_int()
+        self._check(lib().lbm_tile_rows(self._h, ctypes.byref(r)))
+        return r.value
 
     def check(self):
         bad = ctypes.c_uint64()

@@ -56,7 +56,8 @@ def test_fp32_one_step_random(H, orc, dims):
 @pytest.mark.parametrize("rows", [8, 10, 12, 13])
 def test_fp32_tile_heights_agree_with_oracle_and_each_other(H, orc, rows):
     """Every tile height, with ragged tiles in x and y and several z segments,
-    gives the oracle's step and the same bits as the automatic choice."""
+    gives the oracle's step and the same bits as the automatic choice (the
+    height the context times as fastest, which leaves the state alone)."""
     dims = (130, 53, 40)
     _note("fp32 tile rows", rows, dims)
     m = W.random_moments(*dims, seed=21).astype(np.float32)
@@ -65,6 +66,11 @@ def test_fp32_tile_heights_agree_with_oracle_and_each_other(H, orc, rows):
         with H.HomeLBM(dims, 0.57) as s:
             s.set_options(tile_rows=tr)
             s.set_moments(m)
+            before = s.get_raw().copy()
+            assert s.tile_rows == tr  # 0: not timed yet
+            s.prepare(2)  # times the heights when tr is 0; takes no step
+            assert s.step_count == 0 and np.array_equal(s.get_raw(), before)
+            assert s.tile_rows == (tr if tr else s.tile_rows) and s.tile_rows in (8, 10, 12, 13)
             s.step(2)
             outs[tr] = s.get_raw()
     assert np.array_equal(outs[0], outs[rows])
