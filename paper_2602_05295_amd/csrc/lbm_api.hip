@@ -266,9 +266,8 @@ int launch_pass(lbm_ctx* c, const StepParams& p, hipStream_t s, hipEvent_t ev[4]
   if (n > 0) {
     if (ev) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess)
-      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_run), 0, s);
-    if (e == hipSuccess && c->n_solid_b > 0)
-      e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b), s);
+      e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_run),
+                          c->d_cells + c->n_fluid_b, int(c->n_solid_b), s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
@@ -418,7 +417,7 @@ int mixed_requantize(lbm_ctx* c, bool dither, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) e = hipEventRecord(ev0, c->stream);
   if (e == hipSuccess) e = launch_requantize(p, c->N, c->stream);
   if (e == hipSuccess && c->n_solid_b > 0)
-    e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b),
+    e = launch_boundary(c->fmt, p, nullptr, nullptr, nullptr, nullptr, 0, c->d_cells + c->n_fluid_b, int(c->n_solid_b),
                         c->stream);
   if (e == hipSuccess && ev1) e = hipEventRecord(ev1, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "requantize");
@@ -945,7 +944,7 @@ int lbm_set_raw(lbm_ctx* c, const void* in, size_t bytes, int on_device) {
   if (e == hipSuccess && c->n_solid_b > 0) {
     // solid cells next to fluid hold the rest state at every step
     StepParams p = step_params(c, c->buf[c->cur], c->buf[c->cur]);
-    e = launch_boundary(c->fmt, p, c->d_cells + c->n_fluid_b, nullptr, nullptr, nullptr, 0, int(c->n_solid_b),
+    e = launch_boundary(c->fmt, p, nullptr, nullptr, nullptr, nullptr, 0, c->d_cells + c->n_fluid_b, int(c->n_solid_b),
                         c->stream);
   }
   if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);

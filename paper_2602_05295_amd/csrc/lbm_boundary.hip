@@ -61,10 +61,47 @@ __global__ void __launch_bounds__(256) boundary_solid_kernel(StepParams ap, cons
   boundary_solid<FMT>(ap, cells[e]);
 }
 
+// Both lists in one launch: the fluid fixes' workgroups first, then the
+// solid resets', which fill the gaps as the fixes drain.  No cell is in both
+// lists, and a fluid fix reads only the old state (p.in), never a cell a
+// reset writes.
+template <int FMT>
+__global__ void __launch_bounds__(256) boundary_kernel(StepParams ap, const uint32_t* __restrict__ cells,
+                                                       const uint32_t* __restrict__ bits,
+                                                       const uint32_t* __restrict__ yz,
+                                                       const uint32_t* __restrict__ order, int nfluid,
+                                                       const uint32_t* __restrict__ solid_cells, int nsolid) {
+  const int bf = (nfluid + 255) / 256;
+  const int b = int(blockIdx.x);
+  const bool fluid = b < bf;
+  const int k = fluid ? b : b - bf;
+  if (!fluid) {  // the whole workgroup
+    const int e = k * 256 + int(threadIdx.x);
+    if (e < nsolid) boundary_solid<FMT>(ap, solid_cells[e]);
+    return;
+  }
+  StepParams a = ap;
+  a.key = step_key(ap);
+  __shared__ float rest[27];
+  if (threadIdx.x < 27) rest_links<FMT>(a, int(threadIdx.x), rest);
+  __syncthreads();
+  const int t = k * 256 + int(threadIdx.x);
+  if (t >= nfluid) return;
+  const uint32_t e = order ? order[t] : uint32_t(t);
+  boundary_fix<FMT, false, true>(a, e, cells[e], bits[e], yz[e], nullptr, rest);
+}
+
 namespace {
 template <int FMT>
 hipError_t launch_boundary_fmt(const StepParams& p, const uint32_t* cells, const uint32_t* bits, const uint32_t* yz,
-                               const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
+                               const uint32_t* order, int nfluid, const uint32_t* solid_cells, int nsolid,
+                               hipStream_t s) {
+  if (nfluid > 0 && nsolid > 0 && !p.forces) {
+    const dim3 grid(uint32_t((nfluid + 255) / 256 + (nsolid + 255) / 256));
+    hipLaunchKernelGGL(boundary_kernel<FMT>, grid, dim3(256), 0, s, p, cells, bits, yz, order, nfluid, solid_cells,
+                       nsolid);
+    return hipGetLastError();
+  }
   if (nfluid > 0) {
     const dim3 grid(uint32_t((nfluid + 255) / 256));
     if (p.forces)
@@ -76,7 +113,7 @@ hipError_t launch_boundary_fmt(const StepParams& p, const uint32_t* cells, const
   }
   if (nsolid > 0) {
     const dim3 grid(uint32_t((nsolid + 255) / 256));
-    hipLaunchKernelGGL(boundary_solid_kernel<FMT>, grid, dim3(256), 0, s, p, cells + nfluid, nsolid);
+    hipLaunchKernelGGL(boundary_solid_kernel<FMT>, grid, dim3(256), 0, s, p, solid_cells, nsolid);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -84,10 +121,14 @@ hipError_t launch_boundary_fmt(const StepParams& p, const uint32_t* cells, const
 }  // namespace
 
 hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
-                           const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s) {
-  if (fmt == FMT_F32) return launch_boundary_fmt<FMT_F32>(p, cells, bits, yz, order, nfluid, nsolid, s);
+                           const uint32_t* yz, const uint32_t* order, int nfluid, const uint32_t* solid_cells,
+                           int nsolid, hipStream_t s) {
+  if (fmt == FMT_F32)
+    return launch_boundary_fmt<FMT_F32>(p, cells, bits, yz, order, nfluid, solid_cells, nsolid, s);
   hipError_t e = hipErrorInvalidValue;
-  dispatch_codes(fmt, [&]<int F>() { e = launch_boundary_fmt<F>(p, cells, bits, yz, order, nfluid, nsolid, s); });
+  dispatch_codes(fmt, [&]<int F>() {
+    e = launch_boundary_fmt<F>(p, cells, bits, yz, order, nfluid, solid_cells, nsolid, s);
+  });
   return e;
 }
 

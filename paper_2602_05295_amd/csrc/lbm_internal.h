@@ -209,11 +209,13 @@ hipError_t launch_triangle_correction(const StepParams& p, const TriangleSet& T,
 
 // Boundary pass: the nfluid listed fluid cells (list order = slot order,
 // with their y | z << 16 in yz) take the fluid pass's moments from p.lc.side
-// and the corrections of their boundary links; then the nsolid listed solid
-// cells (cells + nfluid) are reset to rest.
+// and the corrections of their boundary links; the nsolid listed solid cells
+// (solid_cells) are reset to rest.  Without force tracking both lists share
+// one launch; the two sets of cells are disjoint.
 // order (may be null): the order in which the fluid entries are visited.
 hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, const uint32_t* bits,
-                           const uint32_t* yz, const uint32_t* order, int nfluid, int nsolid, hipStream_t s);
+                           const uint32_t* yz, const uint32_t* order, int nfluid, const uint32_t* solid_cells,
+                           int nsolid, hipStream_t s);
 
 // Boundary list of one domain whose cells start at global index goff.
 // Count pass (lbase == nullptr): counters[0] / [1] receive the fluid / solid
