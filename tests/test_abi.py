@@ -53,6 +53,17 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert h.value is None
 
 
+def test_null_context_is_refused_by_the_newer_entry_points():
+    """lbm_prepare, lbm_tile_rows and lbm_set_triangles check their arguments
+    before any device call (a NULL context never reaches the GPU)."""
+    L = homelbm.lib()
+    rows = ctypes.c_int(-1)
+    assert L.lbm_prepare(None, 4) == homelbm.ERR_INVALID_ARG
+    assert L.lbm_tile_rows(None, ctypes.byref(rows)) == homelbm.ERR_INVALID_ARG
+    assert rows.value == -1
+    assert L.lbm_set_triangles(None, 0, None, None) == homelbm.ERR_INVALID_ARG
+
+
 def test_no_oracle_in_product_path():
     pkg = os.path.dirname(homelbm.__file__)
     for root, _, files in os.walk(pkg):
