@@ -63,6 +63,11 @@ template <int CTRL>
 __device__ inline float lane_move(float edge, float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
+// The same with zero in a lane without a source (no register to preset).
+template <int CTRL>
+__device__ inline float lane_move0(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 
 // The stored words of one cell: ten floats, or the format's code words.
 template <int FMT, bool F = (FMT == FMT_F32)>
@@ -286,8 +291,7 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams ap, in
         float Y[8][3];
 #pragma unroll
         for (int g = 0; g < 8; ++g)
-          proj3(f0[g], lane_move<DPP_ROW_SHR1>(0.0f, fp[g]), lane_move<DPP_ROW_SHL1>(0.0f, fm[g]), Y[g][0], Y[g][1],
-                Y[g][2]);
+          proj3(f0[g], lane_move0<DPP_ROW_SHR1>(fp[g]), lane_move0<DPP_ROW_SHL1>(fm[g]), Y[g][0], Y[g][1], Y[g][2]);
         if (active && inner) {
           float x0v[9], xp[9], xm[9];
 #pragma unroll
