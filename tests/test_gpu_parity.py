@@ -241,13 +241,14 @@ def _sample_cells(rng, N, mask=None, k=3000, extra=None):
     return cells
 
 
-def _plan_edge_cells(n):
+def _plan_edge_cells(n, rows):
     """Cells of an n^3 grid on the fluid pass's work boundaries: the first and
     last x and y of tiles, the first and last plane of every z segment and of
-    the z tail, as the plan for n^3 lays them out."""
+    the z tail, as the plan for n^3 with `rows`-row tiles (the height the
+    context ran) lays them out."""
     import torch
     from paper_2602_05295_amd import homelbm
-    plan = homelbm.fluid_plan((n, n, n), cus=torch.cuda.get_device_properties(0).multi_processor_count)
+    plan = homelbm.fluid_plan((n, n, n), tile_rows=rows, cus=torch.cuda.get_device_properties(0).multi_processor_count)
     zt = n - plan["tail"]
     zs = set()
     for sg in range(plan["nseg"]):
@@ -277,9 +278,10 @@ def test_fp32_256cubed_sampled(H, orc):
         m0 = s.get_moments()
         s.step(1)
         got = s.get_moments()
+        rows = s.tile_rows
     rng = np.random.default_rng(0)
     cells = _sample_cells(rng, n ** 3, extra=np.concatenate([np.array([0, n - 1, n * n - 1, n ** 3 - 1]),
-                                                             _plan_edge_cells(n)]))
+                                                             _plan_edge_cells(n, rows)]))
     ref = orc.step_cells(_orc_params(orc, (n, n, n), 0.51), m0.astype(np.float64), cells)
     g = got.reshape(10, -1)[:, cells]
     err = group_rel_err(g, ref.T)
@@ -303,9 +305,10 @@ def test_q16_256cubed_sampled(H, orc):
         t0 = s.step_count
         s.step(1)
         got = s.get_raw()
+        rows = s.tile_rows
     rng = np.random.default_rng(2)
     cells = _sample_cells(rng, n ** 3, extra=np.concatenate([np.array([0, n - 1, n * n - 1, n ** 3 - 1]),
-                                                             _plan_edge_cells(n)]))
+                                                             _plan_edge_cells(n, rows)]))
     ref = orc.q16_step_cells(_orc_params(orc, (n, n, n), 0.51), w0, cells, None, t=t0, seed=0, mode=1)
     g = got.reshape(5, -1)[:, cells]
     d = np.abs(unpack(g) - unpack(ref.T))
