@@ -322,11 +322,19 @@ __global__ void __launch_bounds__(256) adjoint_bounce_kernel(AdjParams a, const 
                                                              const uint32_t* __restrict__ bits, int count) {
   const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  uint32_t bb = bits[e] & 0x7FFFFFFu & ~(1u << 13);
-  if (bb == 0u) return;
-  const uint32_t x = cells[e];
-  float g[10];
+  // The lane's loads go out in two round trips: its entry, then everything
+  // at its cell (the adjoint input, the state and the output it adds to,
+  // read up front because the compiler cannot tell that the output planes
+  // do not alias the others; written back once at the end).  An entry with
+  // no bounce-back link (a face cell) adds zero: it is not skipped, so that
+  // no branch waits for the entry's bits before the cell's loads are issued.
+  const uint32_t b0 = bits[e], x = cells[e];
+  float g[10], m[10], acc[10];
   load10(a.lam_in, x, g);
+  load10(a.m, x, m);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = a.lam_out[k][x];
+  uint32_t bb = b0 & 0x7FFFFFFu & ~(1u << 13);
   float gA[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) gA[k] = 0.0f;
@@ -336,15 +344,13 @@ __global__ void __launch_bounds__(256) adjoint_bounce_kernel(AdjParams a, const 
     const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
     add_basis(link_dot(g, cx, cy, cz), -cx, -cy, -cz, gA);
   }
-  float m[10];
-  load10(a.m, x, m);
   float out[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) out[k] = 0.0f;
   const CellLin cl = cell_lin(m, a.om1, nullptr);
   coeffs_T(cl, a.om1, gA, true, out);
 #pragma unroll
-  for (int k = 0; k < 10; ++k) a.lam_out[k][x] += out[k];
+  for (int k = 0; k < 10; ++k) a.lam_out[k][x] = acc[k] + out[k];
 }
 
 // One thread per cell of the two x-face planes (inflow on: x = 0 inflow,
@@ -362,6 +368,11 @@ __global__ void __launch_bounds__(256) adjoint_face_kernel(AdjParams a) {
   const int y = yz % ny, z = yz / ny;
   const int x = out_face ? nx - 1 : 0;
   const uint32_t s = uint32_t(x) + uint32_t(nx) * (uint32_t(y) + uint32_t(ny) * uint32_t(z));
+  // the output this lane adds to, read before any other work (see
+  // adjoint_bounce_kernel) and written back once
+  float acc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = a.lam_out[k][s];
   float gA[NA], gin[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) gA[k] = gin[k] = 0.0f;
@@ -398,7 +409,7 @@ __global__ void __launch_bounds__(256) adjoint_face_kernel(AdjParams a) {
     coeffs_T(cl, a.om1, gin, false, out);
   }
 #pragma unroll
-  for (int k = 0; k < 10; ++k) a.lam_out[k][s] += out[k];
+  for (int k = 0; k < 10; ++k) a.lam_out[k][s] = acc[k] + out[k];
 }
 
 // flags: 1 = listed fluid cell, 2 = solid cell, 0 = other fluid cell
