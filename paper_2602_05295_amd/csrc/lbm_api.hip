@@ -38,6 +38,7 @@ struct lbm_ctx {
   uint4* d_lpack = nullptr;               // the two packed per word for the fluid and boundary passes
   uint32_t* d_order = nullptr;            // boundary pass order of the fluid entries: face cells first
   float* d_side = nullptr;
+  uint32_t* d_solid = nullptr;            // solid bitmap (ListedCells::solid), built with the list
   int64_t n_fluid_b = 0, n_solid_b = 0;
   int64_t n_fluid_run = 0;                // fluid entries the boundary pass visits (d_order's length, if any)
   uint32_t* d_counters = nullptr;     // 3 list counters
@@ -114,7 +115,9 @@ void free_list(lbm_ctx* c) {
   if (c->d_lpack) (void)hipFree(c->d_lpack);
   if (c->d_order) (void)hipFree(c->d_order);
   if (c->d_side) (void)hipFree(c->d_side);
+  if (c->d_solid) (void)hipFree(c->d_solid);
   c->d_cells = c->d_bits = c->d_yz = c->d_lbase = nullptr;
+  c->d_solid = nullptr;
   c->d_lmask = nullptr;
   c->d_lpack = nullptr;
   c->d_order = nullptr;
@@ -205,6 +208,11 @@ int build_list(lbm_ctx* c) {
       run_fluid = int64_t(order.size());
     }
   }
+  if (c->d_mask) {
+    e = hipMalloc(&c->d_solid, size_t((c->N + 31) / 32) * 4);
+    if (e == hipSuccess) e = launch_solid_bits(c->d_mask, uint32_t(c->N), c->d_solid, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "solid bitmap");
+  }
   c->n_fluid_b = cnt[0];
   c->n_fluid_run = run_fluid;
   c->n_solid_b = cnt[1];
@@ -248,6 +256,7 @@ StepParams step_params(const lbm_ctx* c, const void* in, void* out) {
   p.objects = c->d_objects;
   p.forces = c->opt.track_forces ? c->d_forces : nullptr;
   if (c->n_fluid_b > 0) p.lc = ListedCells{c->d_lpack, c->d_side, uint32_t(c->n_fluid_b)};
+  p.lc.solid = c->d_solid;
   return p;
 }
 
@@ -262,12 +271,14 @@ int launch_pass(lbm_ctx* c, const StepParams& p, hipStream_t s, hipEvent_t ev[4]
   if (e == hipSuccess) e = launch_fluid(c->fmt, p, fluid_rows(c), s);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
   if (e != hipSuccess) return hip_fail(c, e, "fluid pass");
-  const int64_t n = c->n_fluid_b + c->n_solid_b;
+  // the fluid pass of an open-face domain wrote the solid cells' rest state
+  const int64_t nsolid = (p.g.inflow && p.lc.solid) ? 0 : c->n_solid_b;
+  const int64_t n = c->n_fluid_b + nsolid;
   if (n > 0) {
     if (ev) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess)
       e = launch_boundary(c->fmt, p, c->d_cells, c->d_bits, c->d_yz, c->d_order, int(c->n_fluid_run),
-                          c->d_cells + c->n_fluid_b, int(c->n_solid_b), s);
+                          c->d_cells + c->n_fluid_b, int(nsolid), s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e != hipSuccess) return hip_fail(c, e, "boundary pass");
   }
@@ -970,7 +981,7 @@ int lbm_memory_bytes(const lbm_ctx* c, size_t* sb, size_t* tb) {
   if (sb) *sb = s;
   if (tb)
     *tb = s + (c->d_ps ? size_t(c->N) * 40 : 0) + size_t(c->n_links) * 4 + (c->d_mask ? size_t(c->N) : 0) + size_t(c->n_fluid_b + c->n_solid_b) * 8 + size_t(c->n_fluid_b) * 52 +
-          (c->d_lmask ? size_t((c->N + 63) / 64) * 28 : 0) + 4 * 4 + 8;
+          (c->d_lmask ? size_t((c->N + 63) / 64) * 28 : 0) + (c->d_solid ? size_t((c->N + 31) / 32) * 4 : 0) + 4 * 4 + 8;
   return LBM_OK;
 }
 

@@ -133,6 +133,23 @@ hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, 
 }
 
 // ------------------------------------------------------------ compaction ---
+// Word w of the solid bitmap holds cells 32 w .. 32 w + 31 (bit k: cell
+// 32 w + k), built from one ballot per wavefront: lanes 0 and 32 write the
+// two words their wavefront covers.  Bits past the last cell are zero.
+__global__ void __launch_bounds__(256) solid_bits_kernel(const uint8_t* __restrict__ mask, uint32_t N,
+                                                         uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const unsigned long long b = __ballot(i < N && mask[i] != 0);
+  const uint32_t lane = threadIdx.x & 63u;
+  if ((lane & 31u) == 0u && i < N) out[i >> 5] = uint32_t(b >> lane);
+}
+
+hipError_t launch_solid_bits(const uint8_t* mask, uint32_t N, uint32_t* out, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(solid_bits_kernel, dim3((N + 255u) / 256u), dim3(256), 0, s, mask, N, out);
+  return hipGetLastError();
+}
+
 // Classifies every cell of a domain.  Listed fluid cells are kept in raster
 // order (their slot comes from the global bitmap and its prefix counts, so
 // the fluid pass can find a cell's slot without searching); listed solid

@@ -120,18 +120,22 @@ __device__ inline void store_word(void* plane, uint32_t off, T v) {
     *p = v;
 }
 
+// rest: the cell is solid, and its words are those of the rest state
+// (zero moments in FP32, the rest codes otherwise) whatever was computed.
 template <int FMT, bool STREAM>
-__device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, const float j[3], const float P[6]) {
+__device__ inline void store_cell(const StepParams& a, uint32_t cell, float dr, const float j[3], const float P[6],
+                                  bool rest = false) {
   const uint32_t off = cell * 4u;
   if constexpr (FMT == FMT_F32) {
     const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
 #pragma unroll
-    for (int k = 0; k < 10; ++k) store_word<float, STREAM>(a.out[k], off, v[k]);
+    for (int k = 0; k < 10; ++k) store_word<float, STREAM>(a.out[k], off, rest ? 0.0f : v[k]);
   } else {
-    uint32_t w[Codec<FMT>::W];
+    uint32_t w[Codec<FMT>::W], r[Codec<FMT>::W];
     Codec<FMT>::encode(dr, j, P, cell, a.key, a.dither != 0, w);
+    rest_codes<FMT>(r);
 #pragma unroll
-    for (int k = 0; k < Codec<FMT>::W; ++k) store_word<uint32_t, STREAM>(a.out[k], off, w[k]);
+    for (int k = 0; k < Codec<FMT>::W; ++k) store_word<uint32_t, STREAM>(a.out[k], off, rest ? r[k] : w[k]);
   }
 }
 
@@ -231,29 +235,39 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams ap, in
     const bool keep = !MIXED && compute && a.lc.side != nullptr;
     const uint32_t row0 = __builtin_amdgcn_readfirstlane(row);  // lane 0: the row's first own cell
     ListedPair lwA{}, lwB{};
+    // Open-face domains: this lane's word of the solid bitmap for the cell
+    // stored next, loaded a plane ahead like the listed-cell words; a solid
+    // cell is stored as the rest state, so the boundary pass resets none.
+    // (The periodic kernels leave the solid cells to the boundary pass and
+    // carry none of this.)
+    const bool solids = FACES && own && a.lc.solid != nullptr;
+    uint32_t swA = 0u, swB = 0u;
     // New moments of the plane finished by the previous step.  They are
     // stored at the start of the next step, after its state has arrived and
     // before its loads are issued: then no store is issued between a plane's
     // loads and their use, and the wait for the loads is a wait for them
     // alone (a store issued later would have to complete as well).
     float sdr = 0.0f, sj[3] = {0.0f, 0.0f, 0.0f}, sP[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    auto store_plane = [&](int ps, const ListedPair& lw) {
+    auto store_plane = [&](int ps, const ListedPair& lw, uint32_t sw) {
       if (own) {
         const uint32_t cell = row + plane * uint32_t(ps);
-        store_cell<OUT, STREAM>(a, cell, sdr, sj, sP);
+        store_cell<OUT, STREAM>(a, cell, sdr, sj, sP, solids && ((sw >> (cell & 31u)) & 1u) != 0u);
         if (keep && (lw.a.x | lw.a.y | lw.b.x | lw.b.y) != 0u) keep_listed(a.lc, cell, lw, sdr, sj, sP);
       }
     };
 
     // One plane p: cur holds its state, nxt receives plane p + 1's; wp2 holds
     // the fp of plane p - 2 and receives this plane's fp; w0in holds the f0 of
-    // plane p - 1, w0out receives this plane's; lw_cur belongs to the cell of
-    // plane p - 2 (stored now), lw_nxt receives that of plane p - 1.
+    // plane p - 1, w0out receives this plane's; lw_cur and sw_cur belong to
+    // the cell of plane p - 2 (stored now), lw_nxt and sw_nxt receive those of
+    // plane p - 1.
     auto plane_step = [&](int p, const Raw<FMT>& cur, Raw<FMT>& nxt, float (&wp2)[6], const float (&w0)[6],
-                          float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt) {
+                          float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt, uint32_t sw_cur,
+                          uint32_t& sw_nxt) {
       state_arrived<FMT>(cur);
-      if (p - 2 >= za) store_plane(p - 2, lw_cur);
+      if (p - 2 >= za) store_plane(p - 2, lw_cur, sw_cur);
       if (keep && p - 1 >= za && p - 1 < zb) lw_nxt = listed_pair(a.lc, row0 + plane * uint32_t(p - 1));
+      if (solids && p - 1 >= za && p - 1 < zb) sw_nxt = a.lc.solid[(row + plane * uint32_t(p - 1)) >> 5];
       if (p + 1 <= zb) nxt = load_raw<FMT>(a, (row + plane * uint32_t(wrap1(p + 1, nz))) * 4u);
 
       float A[NA];
@@ -370,21 +384,21 @@ __global__ void __launch_bounds__((TYR + 3) * RW) fluid_kernel(StepParams ap, in
     // Two planes per trip of the z march, with the paired buffers' roles
     // swapped, so no register is copied from one plane to the next (3% on
     // both formats).  The last step (plane zb) leaves the moments of plane
-    // zb - 1, whose bitmap words it loaded into lwB when it ran as the first
-    // plane of a trip (lwA otherwise).
+    // zb - 1, whose bitmap words it loaded into lwB and swB when it ran as
+    // the first plane of a trip (lwA and swA otherwise).
     // buffers at the start of a trip: state in bufA, fp(p - 2) in wA, fp(p - 1) in wB, f0(p - 1) in zA
     for (int p = za - 1; p <= zb; p += 2) {
-      plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
+      plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB, swA, swB);
       // now fp(p - 1) in wB, fp(p) in wA, f0(p) in zB
-      if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA);
+      if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA, swB, swA);
       // now fp(p) in wA, fp(p + 1) in wB, f0(p + 1) in zA: the trip's starting roles
     }
     const bool last_in_b = ((zb - za) & 1) != 0;  // plane zb ran first in its trip
     if (zb - 1 >= za) {
       if (last_in_b)
-        store_plane(zb - 1, lwB);
+        store_plane(zb - 1, lwB, swB);
       else
-        store_plane(zb - 1, lwA);
+        store_plane(zb - 1, lwA, swA);
     }
   }
 }

@@ -36,6 +36,10 @@ struct ListedCells {
   const uint4* lpack;
   float* side;      // nside records of 12 floats (48 B): the fluid pass's unrounded moments of each listed cell
   uint32_t nside;
+  // One bit per cell, set where the cell is solid: bit (c & 31) of word
+  // c >> 5.  Given to the fluid pass of open-face domains, which then writes
+  // the solid cells' rest state itself (null: the boundary pass does).
+  const uint32_t* solid;
 };
 
 // Side-buffer record of one listed cell: (rho - 1, j, P) and two pad floats,
@@ -225,6 +229,8 @@ hipError_t launch_boundary(int fmt, const StepParams& p, const uint32_t* cells, 
 hipError_t launch_classify(const uint8_t* mask, const Geometry& g, uint32_t goff, uint32_t* counters,
                            unsigned long long* lmask, const uint32_t* lbase, uint32_t* cells_f, uint32_t* bits_f,
                            uint32_t* yz_f, uint32_t* cells_s, uint32_t* bits_s, uint32_t cap_s, hipStream_t s);
+// The solid bitmap of ListedCells::solid for the N cells of mask: (N + 31) / 32 words.
+hipError_t launch_solid_bits(const uint8_t* mask, uint32_t N, uint32_t* out, hipStream_t s);
 
 // Codec / initialisation / read-back.
 hipError_t launch_set_moments(int fmt, const float* m, void* const out[10], const uint8_t* mask, int64_t N,

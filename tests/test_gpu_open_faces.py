@@ -7,6 +7,8 @@ nothing.  Which lane plays that column depends on nx: with nx a multiple of
 the 64-cell tile width it is the halo-column wavefront, otherwise a lane of
 the last tile's row wavefronts.  Both are covered, with one tile and several
 along x, with and without solids and a body force, in both storage formats.
+With open faces the fluid pass also stores every solid cell as the rest state
+(the oracle's solid cells hold it), interior solid cells included.
 """
 import numpy as np
 import pytest
@@ -104,3 +106,26 @@ def test_fp32_open_faces_without_solids(H, orc):
     ref = orc.run(orc.make_params(dims, 0.6, inflow=True, u_in=U_IN), m0.astype(np.float64), 4)
     err = group_rel_err(got, ref)
     assert max(err.values()) <= TOL32, err
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+@pytest.mark.parametrize("dims", [(64, 14, 9), (70, 13, 8)])
+def test_solid_cells_hold_the_rest_state(H, dims, fmt):
+    """A box obstacle with interior cells and small spheres, three steps with
+    open faces: every solid cell's stored words equal those of the rest state
+    (what a context at rest, rho = 1 and u = 0, holds there)."""
+    _note("solid cells at rest", dims, fmt)
+    nx, ny, nz = dims
+    mask = _mask(dims, seed=nx + 7)
+    mask[2:6, 3:10, 20:30] = 1  # interior cells: z 3..4, y 4..8, x 21..28
+    solid = mask == 1
+    m = W.random_moments(*dims, seed=13, dj=0.02, dp=0.003).astype(np.float32)
+    with H.HomeLBM(dims, 0.6, mask=mask, fmt=fmt) as s:
+        s.set_options(inflow=True, u_in=U_IN, dither_mode=1 if fmt == "q16" else 0, seed=3)
+        s.set_moments(m)
+        s.step(3)
+        got = s.get_raw().copy()
+    with H.HomeLBM(dims, 0.6, mask=mask, fmt=fmt) as r:
+        r.set_equilibrium(np.ones((nz, ny, nx), np.float32), np.zeros((3, nz, ny, nx), np.float32))
+        rest = r.get_raw().copy()
+    assert np.array_equal(got[:, solid], rest[:, solid])
