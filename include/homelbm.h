@@ -272,7 +272,12 @@ int lbm_set_step_count(lbm_ctx* ctx, uint64_t t);
  */
 int lbm_memory_bytes(const lbm_ctx* ctx, size_t* state_bytes, size_t* total_bytes);
 
-/* Sizes of the boundary list: fluid cells recomputed by the boundary pass and solid cells reset to rest. */
+/*
+ * Sizes of the boundary list: fluid cells recomputed by the boundary pass, and
+ * solid cells next to fluid, which hold the rest state at the start of every
+ * step (reset by the boundary pass; with the inflow on, the fluid pass stores
+ * every solid cell as the rest state and the boundary pass visits none).
+ */
 int lbm_boundary_counts(const lbm_ctx* ctx, int64_t* fluid_cells, int64_t* solid_cells);
 
 /*
