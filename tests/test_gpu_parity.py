@@ -318,7 +318,7 @@ def test_q16_256cubed_sampled(H, orc):
 
 def test_q16_channel_sampled(H, orc):
     """The 1000x400x400 obstacle channel in Q16, one step, sampled cells
-    including boundary cells."""
+    including boundary cells, and sampled solid cells."""
     nx, ny, nz = 1000, 400, 400
     _note("q16 channel 1000x400x400 sampled")
     mask = W.channel_mask(nx, ny, nz, seed=0)
@@ -346,6 +346,10 @@ def test_q16_channel_sampled(H, orc):
     d = np.abs(unpack(g.T) - unpack(ref.T))
     assert d.max() <= 1, d.max()
     assert (d > 0).mean() < 0.01, (d > 0).mean()
+    # solid cells, interior ones included, hold the oracle's rest codes
+    sol = np.unique(rng.choice(solid_idx, 2000))
+    ref_s = orc.q16_step_cells(P, w0, sol, mask, t=t0, seed=3, mode=1)
+    assert np.array_equal(got.reshape(5, -1)[:, sol].T, ref_s)
 
 
 # ------------------------------------------------------------- interfaces ---
