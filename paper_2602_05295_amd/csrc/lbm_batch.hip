@@ -76,18 +76,20 @@ __device__ inline void bstore_word(void* plane, uint32_t byte_off, T v) {
     *q = v;
 }
 
+// rest: a solid cell, stored as the rest state whatever was computed.
 template <int FMT, bool STREAM>
 __device__ inline void bstore(const BatchStepParams& a, uint32_t byte_off, uint32_t cell, uint32_t key, bool dith,
-                              float dr, const float j[3], const float P[6]) {
+                              float dr, const float j[3], const float P[6], bool rest) {
   if constexpr (FMT == FMT_F32) {
     const float v[10] = {dr, j[0], j[1], j[2], P[0], P[1], P[2], P[3], P[4], P[5]};
 #pragma unroll
-    for (int k = 0; k < 10; ++k) bstore_word<float, STREAM>(a.out[k], byte_off, v[k]);
+    for (int k = 0; k < 10; ++k) bstore_word<float, STREAM>(a.out[k], byte_off, rest ? 0.0f : v[k]);
   } else {
-    uint32_t w[5];
+    uint32_t w[5], r[5];
     encode_cell(dr, j, P, cell, key, dith, w);
+    rest_codes<FMT_Q16>(r);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) bstore_word<uint32_t, STREAM>(a.out[k], byte_off, w[k]);
+    for (int k = 0; k < 5; ++k) bstore_word<uint32_t, STREAM>(a.out[k], byte_off, rest ? r[k] : w[k]);
   }
 }
 
@@ -148,25 +150,33 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
     if (active) bufA = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(za - 1, nz))) * 4u);
     const bool keep = own && a.lc.side != nullptr;  // listed cells to look for
     ListedPair lwA{}, lwB{};                        // packed bitmap words of the cells stored next
+    // this lane's word of the solid bitmap for the cell stored next, loaded
+    // a plane ahead: a solid cell is stored as the rest state
+    const bool solids = own && a.lc.solid != nullptr;
+    uint32_t swA = 0u, swB = 0u;
     // new moments of the plane finished by the previous step
     float sdr = 0.0f, sj[3] = {0.0f, 0.0f, 0.0f}, sP[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    auto store_plane = [&](int ps, const ListedPair& lws) {
+    auto store_plane = [&](int ps, const ListedPair& lws, uint32_t sws) {
       if (own) {
         const uint32_t cell = rowc + plane * uint32_t(ps);
-        bstore<FMT, STREAM>(a, (D.off + cell) * 4u, cell, key, dith, sdr, sj, sP);
+        bstore<FMT, STREAM>(a, (D.off + cell) * 4u, cell, key, dith, sdr, sj, sP,
+                            solids && ((sws >> ((D.off + cell) & 31u)) & 1u) != 0u);
         const int slot = keep ? listed_slot_in(listed_word(lws, D.off + cell), D.off + cell) : -1;
         if (slot >= 0) side_store(a.lc.side, uint32_t(slot), sdr, sj, sP);  // a listed cell's unrounded moments
       }
     };
     // One plane p: cur holds its state, nxt receives plane p + 1's; wp2 holds
     // the fp of plane p - 2 and receives this plane's; w0 holds the f0 of plane
-    // p - 1, w0out receives this plane's; lw_cur belongs to the cell of plane
-    // p - 2 (stored now), lw_nxt receives that of plane p - 1.
+    // p - 1, w0out receives this plane's; lw_cur and sw_cur belong to the cell
+    // of plane p - 2 (stored now), lw_nxt and sw_nxt receive those of plane
+    // p - 1.
     auto plane_step = [&](int p, const BRaw<FMT>& cur, BRaw<FMT>& nxt, float (&wp2)[6], const float (&w0)[6],
-                          float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt) {
+                          float (&w0out)[6], const ListedPair& lw_cur, ListedPair& lw_nxt, uint32_t sw_cur,
+                          uint32_t& sw_nxt) {
       bstate_arrived<FMT>(cur);
-      if (p - 2 >= za) store_plane(p - 2, lw_cur);
+      if (p - 2 >= za) store_plane(p - 2, lw_cur, sw_cur);
       if (keep && p - 1 >= za && p - 1 < zb) lw_nxt = listed_pair(a.lc, D.off + rowc + plane * uint32_t(p - 1));
+      if (solids && p - 1 >= za && p - 1 < zb) sw_nxt = a.lc.solid[(D.off + rowc + plane * uint32_t(p - 1)) >> 5];
       if (active && p + 1 <= zb) nxt = bload<FMT>(a, (D.off + rowc + plane * uint32_t(wrap1b(p + 1, nz))) * 4u);
 
       float f0[8];
@@ -253,16 +263,16 @@ __global__ void __launch_bounds__(NT) strip_kernel(BatchStepParams a) {
 
     // at the start of a trip: state in bufA, fp(p - 2) in wA, fp(p - 1) in wB, f0(p - 1) in zA
     for (int p = za - 1; p <= zb; p += 2) {
-      plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB);
-      if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA);
+      plane_step(p, bufA, bufB, wA, zA, zB, lwA, lwB, swA, swB);
+      if (p + 1 <= zb) plane_step(p + 1, bufB, bufA, wB, zB, zA, lwB, lwA, swB, swA);
     }
-    // the last step (plane zb) loaded the words of plane zb - 1 into lwB when
-    // it ran first in its trip, else into lwA
+    // the last step (plane zb) loaded the words of plane zb - 1 into lwB and
+    // swB when it ran first in its trip, else into lwA and swA
     if (zb - 1 >= za) {
       if (((zb - za) & 1) != 0)
-        store_plane(zb - 1, lwB);
+        store_plane(zb - 1, lwB, swB);
       else
-        store_plane(zb - 1, lwA);
+        store_plane(zb - 1, lwA, swA);
     }
   }
 }

@@ -180,6 +180,7 @@ struct lbm_batch {
   unsigned long long* d_lmask = nullptr;  // listed fluid cells: bitmap, prefix counts, side buffer
   uint32_t* d_lbase = nullptr;
   uint4* d_lpack = nullptr;               // the two packed per word for the fluid and boundary passes
+  uint32_t* d_solid = nullptr;            // solid bitmap (ListedCells::solid): the fluid pass stores solid cells at rest
   float* d_side = nullptr;
   int64_t n_fluid_b = 0, n_solid_b = 0;
   uint32_t* d_counters = nullptr;
@@ -250,6 +251,7 @@ BatchStepParams params(const lbm_batch* b, int src, uint32_t k) {
   p.stream_out = stream_out_state(plane_bytes(b) * size_t(nplanes(b)));
   p.nwg = b->nwg;
   if (b->n_fluid_b > 0) p.lc = ListedCells{b->d_lpack, b->d_side, uint32_t(b->n_fluid_b)};
+  p.lc.solid = b->d_solid;
   return p;
 }
 
@@ -287,7 +289,9 @@ int apply_tuning(lbm_batch* b, int block, int wgpc) {
 // Launches n steps (fluid + boundary each, then the counter advance) on s,
 // starting from buffer `src`.  ev (optional): 4 events per step.
 int enqueue_steps(lbm_batch* b, int n, int src, hipStream_t s, hipEvent_t* ev) {
-  const int64_t nb = b->n_fluid_b + b->n_solid_b;
+  // the fluid pass stores the solid cells at rest when it has their bitmap
+  const int64_t nsolid = b->d_solid ? 0 : b->n_solid_b;
+  const int64_t nb = b->n_fluid_b + nsolid;
   hipError_t e = hipSuccess;
   for (int k = 0; k < n && e == hipSuccess; ++k) {
     const BatchStepParams p = params(b, (src + k) & 1, uint32_t(k));
@@ -297,7 +301,7 @@ int enqueue_steps(lbm_batch* b, int n, int src, hipStream_t s, hipEvent_t* ev) {
     if (e == hipSuccess && ev) e = hipEventRecord(ev[4 * k + 2], s);
     if (e == hipSuccess && nb > 0)
       e = launch_batch_boundary(b->fmt, p, b->d_cells, b->d_bits, b->d_yz, b->d_dom, int(b->n_fluid_b),
-                                int(b->n_solid_b), s);
+                                int(nsolid), s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[4 * k + 3], s);
   }
   if (e == hipSuccess && n > 0) e = launch_step_advance(b->d_step, uint32_t(n), s);
@@ -422,6 +426,9 @@ int build_lists(lbm_batch* b) {
   }
   b->n_fluid_b = nf_all;
   b->n_solid_b = total - nf_all;
+  e = hipMalloc(&b->d_solid, size_t((b->N + 31) / 32) * 4);
+  if (e == hipSuccess) e = launch_solid_bits(b->d_mask, uint32_t(b->N), b->d_solid, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "solid bitmap");
   return LBM_OK;
 }
 
@@ -644,7 +651,7 @@ int lbm_batch_destroy(lbm_batch* b) {
   for (int k = 0; k < 2; ++k)
     if (b->buf[k]) (void)hipFree(b->buf[k]);
   void* ptrs[] = {b->d_mask,  b->d_cells, b->d_bits, b->d_yz,       b->d_dom,  b->d_lmask, b->d_lbase, b->d_lpack,
-                  b->d_side,  b->d_counters, b->d_bad, b->d_step, b->d_doms, b->d_segs,  b->d_wg_first};
+                  b->d_side,  b->d_solid, b->d_counters, b->d_bad, b->d_step, b->d_doms, b->d_segs, b->d_wg_first};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -894,6 +901,7 @@ int lbm_batch_memory_bytes(const lbm_batch* b, size_t* state_bytes, size_t* tota
   if (total_bytes)
     *total_bytes = s + (b->d_mask ? size_t(b->N) : 0) + size_t(b->n_fluid_b + b->n_solid_b) * 10 +
                    size_t(b->n_fluid_b) * 52 + (b->d_lmask ? size_t((b->N + 63) / 64) * 28 : 0) +
+                   (b->d_solid ? size_t((b->N + 31) / 32) * 4 : 0) +
                    b->plan.segs.size() * sizeof(BatchSeg) + b->plan.wg_first.size() * 4 +
                    size_t(b->count) * sizeof(BatchDomain) + 32;
   return LBM_OK;
