@@ -465,6 +465,9 @@ int lbm_batch_step_eager(lbm_batch* b, int n);
 int lbm_batch_profile_steps(lbm_batch* b, int n, double* fluid_ms, double* boundary_ms);
 int lbm_batch_get_step_count(const lbm_batch* b, uint64_t* t);
 int lbm_batch_set_step_count(lbm_batch* b, uint64_t t);
+/* Sizes of the batch's boundary list: fluid cells the boundary pass recomputes,
+ * and solid cells next to fluid (the fluid pass stores every solid cell as the
+ * rest state, so the boundary pass visits none of them). */
 int lbm_batch_boundary_counts(const lbm_batch* b, int64_t* fluid_cells, int64_t* solid_cells);
 int lbm_batch_memory_bytes(const lbm_batch* b, size_t* state_bytes, size_t* total_bytes);
 int lbm_batch_check(lbm_batch* b, uint64_t* bad);
