@@ -123,7 +123,7 @@ def test_rollout_gradient_matches_oracle(orc, torch_mod):
         loss = 0.5 * (((vel - t) ** 2).sum(0) * w).sum()
         loss.backward()
         g_gpu = u.grad.detach().cpu().numpy().astype(np.float64)
-        loss_gpu = float(loss)
+        loss_gpu = float(loss.detach())
     P = orc.make_params((n, n, n), 0.6)
     g_orc, loss_orc = _oracle_gradient(orc, P, mask, u0.astype(np.float32).astype(np.float64), tgt, T)
     assert abs(loss_gpu - loss_orc) / loss_orc < 1e-4
