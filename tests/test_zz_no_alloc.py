@@ -48,6 +48,21 @@ def test_noalloc_adjoint_equals_adjoint_step():
         assert np.array_equal(got, ref), np.abs(got - ref).max()
 
 
+def test_noalloc_adjoint_seeded_sequence():
+    """Eight contexts in a row with seeded shapes, growing and shrinking,
+    spheres always and open faces or not: every call equals lbm_adjoint_step."""
+    import torch
+    from paper_2602_05295_amd import homelbm as H
+    rng = np.random.default_rng(17)
+    for k in range(8):
+        dims = (int(rng.integers(8, 80)), int(rng.integers(6, 40)), int(rng.integers(6, 30)))
+        inflow = bool(rng.integers(0, 2))
+        print("CASE noalloc adjoint sequence", k, dims, inflow, flush=True)
+        ref, got = _case(torch, H, dims, 100 + k, inflow)
+        assert np.all(np.isfinite(ref))
+        assert np.array_equal(got, ref), (k, np.abs(got - ref).max())
+
+
 def test_noalloc_adjoint_rejects_what_it_cannot_do():
     import torch
     from paper_2602_05295_amd import homelbm as H
