@@ -94,3 +94,27 @@ def test_batch_sweep_case(H, orc, case):
                     diff = diff[:, masks[k] == 0]
                 assert diff.max() <= 1, (s, k, d, diff.max())
                 assert (diff > 0).sum() <= max(3, 0.01 * diff.size), (s, k, d, (diff > 0).sum(), diff.size)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(0, CASES, 3))
+def test_batch_sweep_graphs_equal_eager(H, case):
+    """The same batch stepped through its captured graphs and kernel by
+    kernel: the same bits in every domain after each of three step calls."""
+    c = draw(case)
+    print("CASE batch sweep graphs", case, c["fmt"], "block", c["block"], len(c["dims"]), flush=True)
+    out = {}
+    for eager in (False, True):
+        with H.HomeLBMBatch(c["dims"], c["taus"], c["masks"], fmt=c["fmt"]) as b:
+            b.set_options(dither_mode=c["mode"], seed=c["seed"])
+            b.set_tuning(c["block"], 1)
+            for k, d in enumerate(c["dims"]):
+                b.set_moments(k, W.random_moments(*d, seed=7 * case + k, dj=0.02, dp=0.003).astype(np.float32))
+            states = []
+            for n in (1, 9, 4):
+                (b.step_eager if eager else b.step)(n)
+                states.append([b.get_raw(k).copy() for k in range(len(c["dims"]))])
+            out[eager] = states
+    for s, (g, e) in enumerate(zip(out[False], out[True])):
+        for k in range(len(c["dims"])):
+            assert np.array_equal(g[k], e[k]), (case, s, k)
