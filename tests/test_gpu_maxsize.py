@@ -120,3 +120,52 @@ def test_q16_step_at_the_largest_domain(orc):
     del raw
     torch.cuda.empty_cache()
     assert mismatch == mismatch_inside, (mismatch, mismatch_inside)
+
+
+def test_q16_batch_at_the_largest_total_size(orc):
+    """Four 256 x 1024 x 1024 domains, 2^30 cells together: the last domain's
+    cells sit at the highest offsets of the batch's state planes.  A blob
+    straddles the periodic corner of the first and of the last domain; the
+    bars are those of the single-domain test above."""
+    import torch
+    from paper_2602_05295_amd import homelbm as H
+    d = (256, N, N)
+    dims = [d] * 4
+    print("CASE max size q16 batch", dims, flush=True)
+    o = (d[0] - 8, N - 8, N - 8)
+    ms = _blobs()[0]
+    ix = [torch.tensor([(o[a] + i) % d[a] for i in range(S)], device="cuda") for a in range(3)]
+    zi, yi, xi = ix[2][:, None, None], ix[1][None, :, None], ix[0][None, None, :]
+    with H.HomeLBMBatch(dims, [0.6] * 4, None, fmt="q16") as b:
+        b.set_options(dither_mode=0)
+        b.set_tuning(1024, 1)
+        for k in range(4):
+            m = torch.zeros((10, d[2], d[1], d[0]), device="cuda")
+            m[0] = 1.0
+            if k in (0, 3):
+                m[:, zi, yi, xi] = torch.from_numpy(ms.astype(np.float32)).cuda()
+            b.set_moments(k, m)
+            del m
+        torch.cuda.empty_cache()
+        raw = torch.empty((5, d[2], d[1], d[0]), dtype=torch.int32, device="cuda")
+        b.get_raw(0, out=raw)
+        b.synchronize()
+        w_in = raw[:, zi, yi, xi].cpu().numpy().view(np.uint32).copy()
+        b.step(1)
+        ref = orc.q16_step(orc.make_params((S, S, S), 0.6), w_in, None, t=0, seed=0, mode=0)
+        far = ref[:, 0, 0, 0].copy()
+        far32 = far.view(np.int32)
+        for k in range(4):
+            b.get_raw(k, out=raw)
+            b.synchronize()
+            mismatch = sum(int(torch.count_nonzero(raw[w] != int(far32[w]))) for w in range(5))
+            if k in (0, 3):
+                got = raw[:, zi, yi, xi].cpu().numpy().view(np.uint32)
+                dd = np.abs(unpack(got) - unpack(ref))
+                assert dd.max() <= 1, (k, dd.max())
+                assert (dd > 0).mean() < 0.01, (k, (dd > 0).mean())
+                assert mismatch == int(np.count_nonzero(got != far[:, None, None, None])), k
+            else:
+                assert mismatch == 0, k
+        del raw
+    torch.cuda.empty_cache()
