@@ -118,3 +118,41 @@ def test_batch_sweep_graphs_equal_eager(H, case):
     for s, (g, e) in enumerate(zip(out[False], out[True])):
         for k in range(len(c["dims"])):
             assert np.array_equal(g[k], e[k]), (case, s, k)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fmt", ["fp32", "q16"])
+def test_batch_of_many_tiny_domains(H, orc, fmt):
+    """3000 domains of 1..6 cells a side, many to a workgroup and packed
+    across wavefront boundaries, spheres in some: every domain against the
+    oracle after one step (16-bit from identical codes)."""
+    rng = np.random.default_rng(21)
+    dims = [tuple(int(v) for v in rng.integers(1, 7, 3)) for _ in range(3000)]
+    taus = [float(v) for v in rng.uniform(0.52, 0.9, len(dims))]
+    masks = []
+    for k, d in enumerate(dims):
+        mk = None
+        if min(d) >= 4 and k % 3 == 0:
+            mk = W.sphere_mask(*d, phi=0.1, rmin=0.8, rmax=1.5, seed=k)
+            if not mk.any() or mk.all():
+                mk = None
+        masks.append(mk)
+    print("CASE batch many tiny domains", fmt, len(dims), sum(m is not None for m in masks), flush=True)
+    with H.HomeLBMBatch(dims, taus, masks, fmt=fmt) as b:
+        b.set_options(dither_mode=1, seed=5)
+        for k, d in enumerate(dims):
+            b.set_moments(k, W.random_moments(*d, seed=k, dj=0.02, dp=0.003).astype(np.float32))
+        b.step_count = 3
+        before = [(b.get_moments(k) if fmt == "fp32" else b.get_raw(k)).copy() for k in range(len(dims))]
+        b.step(1)
+        for k, d in enumerate(dims):
+            P = orc.make_params(d, taus[k])
+            if fmt == "fp32":
+                err = group_rel_err(b.get_moments(k), orc.step(P, before[k].astype(np.float64), masks[k]))
+                assert max(err.values()) <= 1e-5, (k, d, err)
+            else:
+                ref = orc.q16_step(P, before[k], masks[k], t=3, seed=5, mode=1)
+                diff = np.abs(unpack(b.get_raw(k)) - unpack(ref))
+                if masks[k] is not None:
+                    diff = diff[:, masks[k] == 0]
+                assert diff.max() <= 1, (k, d, diff.max())
