@@ -53,6 +53,32 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert h.value is None
 
 
+def test_batch_create_rejects_bad_arguments_before_touching_the_device():
+    """An empty batch, an empty or oversized domain, tau <= 1/2, a domain too
+    wide for the strip kernel and more than 2^30 cells in all are refused with
+    a message, before any device call."""
+    L = homelbm.lib()
+    h = ctypes.c_void_p()
+
+    def create(dims_list, taus, fmt=homelbm.Q16):
+        flat = (ctypes.c_int * (3 * max(1, len(dims_list))))(*[v for d in dims_list for v in d])
+        tau = (ctypes.c_double * max(1, len(taus)))(*taus)
+        return L.lbm_batch_create(len(dims_list), flat, tau, None, fmt, ctypes.byref(h))
+
+    assert create([], []) == homelbm.ERR_INVALID_ARG
+    assert b"count" in L.lbm_batch_last_error(None)
+    assert create([(4, 0, 4)], [0.6]) == homelbm.ERR_INVALID_ARG
+    assert b"dimensions" in L.lbm_batch_last_error(None)
+    assert create([(4, 4, 4), (4, 4, 70000)], [0.6, 0.6]) == homelbm.ERR_INVALID_ARG
+    assert create([(4, 4, 4)], [0.5]) == homelbm.ERR_INVALID_ARG
+    assert b"tau" in L.lbm_batch_last_error(None)
+    assert create([(342, 4, 4)], [0.6]) == homelbm.ERR_INVALID_ARG
+    assert b"341" in L.lbm_batch_last_error(None)
+    assert create([(256, 1024, 1024)] * 4 + [(1, 1, 1)], [0.6] * 5) == homelbm.ERR_INVALID_ARG
+    assert b"2^30" in L.lbm_batch_last_error(None)
+    assert h.value is None
+
+
 def test_null_context_is_refused_by_the_newer_entry_points():
     """lbm_prepare, lbm_tile_rows and lbm_set_triangles check their arguments
     before any device call (a NULL context never reaches the GPU)."""
